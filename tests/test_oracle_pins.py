@@ -1,0 +1,557 @@
+"""Pins of the FP64 CPU oracle against what the paper and mathematics fix.
+
+None of these re-types the oracle's own formula: each checks it against an
+independent construction (quadrature nodes, the paper's separately printed
+sextic/quintic, the D1Q2 closed form, invariants, limits, brute force).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from tests._states import null_space_direction, perturbed_state
+
+THETA0 = 1.0 / 3.0
+
+
+# --------------------------------------------------------------------------
+# Lattice and equilibrium (Sec. II)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_weight_moment_conditions(D):
+    """<w,1> = 1, <w,c c> = theta0 delta, <w,cccc> = theta0^2 Delta (Sec. II)."""
+    c, w = oracle.lattice(D)
+    c = c[:, :D].astype(float)
+    assert abs(w.sum() - 1.0) < 1e-15
+    np.testing.assert_allclose(np.einsum("i,ia,ib->ab", w, c, c), THETA0 * np.eye(D), atol=1e-15)
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    d = np.eye(D)
+    delta4 = (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+              + np.einsum("ad,bc->abcd", d, d))
+    np.testing.assert_allclose(m4, THETA0 ** 2 * delta4, atol=1e-15)
+    # odd moments vanish
+    np.testing.assert_allclose(np.einsum("i,ia->a", w, c), 0.0, atol=1e-16)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_lattice_index_convention(D):
+    c, _ = oracle.lattice(D)
+    Q = len(c)
+    for i in range(Q):
+        np.testing.assert_array_equal(c[Q - 1 - i], -c[i])  # opposite = Q-1-i
+        assert i == sum((c[i, a] + 1) * 3 ** a for a in range(D))  # x fastest
+    assert np.all(c[(Q - 1) // 2] == 0)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_equilibrium_exact_moments(D):
+    """The product form conserves rho and rho u exactly (Sec. II)."""
+    rng = np.random.default_rng(11 + D)
+    c, _ = oracle.lattice(D)
+    for _ in range(50):
+        rho = 0.5 + rng.random()
+        u = rng.uniform(-0.3, 0.3, D)
+        feq = oracle.equilibrium(D, rho, u)
+        assert np.all(feq > 0)
+        assert abs(feq.sum() - rho) < 2e-15 * rho
+        np.testing.assert_allclose(feq @ c[:, :D], rho * u, atol=2e-15)
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_equilibrium_is_constrained_entropy_minimiser(D):
+    """f^eq = w rho exp(affine in c) (Eq. entropiceqdef), hence the unique
+    minimiser of H at fixed rho, rho u: log(f/w) is affine in c and any
+    moment-preserving perturbation raises H."""
+    rng = np.random.default_rng(5)
+    c, w = oracle.lattice(D)
+    A = np.hstack([np.ones((len(c), 1)), c[:, :D]])
+    for _ in range(20):
+        rho, u = 0.7 + 0.6 * rng.random(), rng.uniform(-0.25, 0.25, D)
+        feq = oracle.equilibrium(D, rho, u)
+        y = np.log(feq / w)
+        coef, *_ = np.linalg.lstsq(A, y, rcond=None)
+        assert np.max(np.abs(A @ coef - y)) < 1e-13
+        Hf = lambda f: float(np.sum(f * (np.log(f / w) - 1)))
+        for _ in range(5):
+            d = null_space_direction(D, rng) * 1e-3 * feq.min()
+            assert Hf(feq + d) > Hf(feq)
+
+
+def test_d1q3_equilibrium_matches_closed_form():
+    """D1Q3 explicit equilibrium of Sec. II: f0 = 4 rho Upsilon / 6 and
+    f_{+-1} = (rho/6) Upsilon z^{+-1}; here checked through the relations
+    it implies: f1 f-1 = (f0/4)^2 (Upsilon^2/36 each side) and f1 - f-1 = rho u."""
+    for u in np.linspace(-0.5, 0.5, 11):
+        feq = oracle.equilibrium(1, 1.3, [u])
+        fm, f0, fp = feq
+        assert abs(fp * fm - (f0 / 4.0) ** 2) < 1e-15
+        assert abs(fp - fm - 1.3 * u) < 1e-15
+        ups = 2 - math.sqrt(1 + 3 * u * u)
+        assert abs(f0 - 4 * 1.3 * ups / 6) < 1e-15
+
+
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_equilibrium_matches_polynomial_to_second_order(D):
+    """f^eq agrees with the polynomial equilibrium of Eq. histeq up to O(u^2)
+    (Sec. II): the remainder scales like u^3.
+
+    Reading: the cubic term printed after it is the continuous (Hermite)
+    one, not the lattice series -- on D1Q3 it would make f_1 - f_-1 = u + u^3
+    and break momentum conservation -- so only the O(u^2) agreement is pinned.
+    """
+    c, w = oracle.lattice(D)
+    c = c[:, :D].astype(float)
+    rng = np.random.default_rng(2)
+    direction = rng.standard_normal(D)
+    direction /= np.linalg.norm(direction)
+
+    def histeq(u):
+        cu = c @ u
+        return w * (1 + cu / THETA0 + (cu ** 2 - THETA0 * (u @ u)) / (2 * THETA0 ** 2))
+
+    errs = []
+    for s in (0.04, 0.02, 0.01):
+        u = s * direction
+        errs.append(np.max(np.abs(oracle.equilibrium(D, 1.0, u) - histeq(u))))
+    # halving u divides the remainder by ~2^3 (2^4 for D1Q3, whose cubic
+    # term vanishes: f_1 - f_-1 = u exactly)
+    lo, hi = (14.0, 18.0) if D == 1 else (7.0, 9.5)
+    assert lo < errs[0] / errs[1] < hi
+    assert lo < errs[1] / errs[2] < hi
+
+
+# --------------------------------------------------------------------------
+# Entropy changes, mirror state and the ELBM root (Sec. III, App. A)
+# --------------------------------------------------------------------------
+def test_dH_matches_direct_H_difference():
+    """App. A: <f,(1+ax)log(1+ax)> - a<f, x log(1+x)> equals H[f + a b (feq - f)] - H[f]."""
+    rng = np.random.default_rng(3)
+    for D in (1, 2, 3):
+        _, w = oracle.lattice(D)
+        Hf = lambda f: float(np.sum(f * (np.log(f / w) - 1)))
+        for _ in range(10):
+            g, feq = perturbed_state(D, 0.02, rng)
+            for alpha, beta in ((2.0, 1.0), (1.7, 0.9), (2.1, 0.99)):
+                direct = Hf(g + alpha * beta * (feq - g)) - Hf(g)
+                assert abs(oracle.dH_step(g, feq, alpha, beta) - direct) < 1e-13
+
+
+def _golden(name):
+    import os
+    rows = []
+    with open(os.path.join(os.path.dirname(__file__), "golden", name)) as fh:
+        for line in fh:
+            line = line.split("#")[0].strip()
+            if line:
+                rows.append(line.split())
+    return rows
+
+
+_D1Q2 = [tuple(float(v) for v in r) for r in _golden("d1q2_mirror_root.txt")]
+
+
+@pytest.mark.parametrize("rho,u,root", _D1Q2)
+def test_d1q2_root_is_two(rho, u, root):
+    """D1Q2 (Sec. III): the non-trivial root of dH = 0 is alpha = 2 for every u,
+    and dH/rho follows the printed closed form."""
+    g = np.array([rho * (1 + u) / 2, rho * (1 - u) / 2])
+    feq = np.array([rho / 2, rho / 2])
+    assert abs(oracle.alpha_elbm(g, feq) - root) < 1e-12
+    for alpha in (0.5, 1.3, 1.9):
+        closed = ((1 + u - alpha * u) / 2 * math.log((1 + u - alpha * u) / (1 + u))
+                  + (1 - u + alpha * u) / 2 * math.log((1 - u + alpha * u) / (1 - u))
+                  + alpha * u / 2 * math.log((1 - u) / (1 + u)))
+        assert abs(oracle.dH_mirror(g, feq, alpha) / rho - closed) < 1e-14
+
+
+def test_near_equilibrium_mirror_quadratic():
+    """dH = alpha(alpha/2 - 1) <f, x^2> + O(x^3) (Sec. III)."""
+    rng = np.random.default_rng(4)
+    d = null_space_direction(2, rng)
+    for eps in (1e-2, 1e-3):
+        g, feq = perturbed_state(2, eps, rng, rho=1.0, u=np.array([0.03, -0.02]), direction=d)
+        x = feq / g - 1
+        fx2 = float(np.sum(g * x * x))
+        for alpha in (1.5, 2.5):
+            lead = alpha * (alpha / 2 - 1) * fx2
+            rel = abs(oracle.dH_mirror(g, feq, alpha) - lead) / abs(lead)
+            assert rel < 30 * np.max(np.abs(x))
+
+
+def test_elbm_root_limit_and_newton():
+    """alpha_ELBM -> 2 + <f,x^3>/(3<f,x^2>) + O(x^2)  (expansion of Eq. deltaH_),
+    and the bisection root satisfies dH = 0."""
+    rng = np.random.default_rng(5)
+    d = null_space_direction(3, rng)
+    prev = None
+    for eps in (4e-3, 2e-3, 1e-3):
+        g, feq = perturbed_state(3, eps, rng, rho=1.0, u=np.array([0.02, 0.01, -0.03]), direction=d)
+        x = feq / g - 1
+        a = oracle.alpha_elbm(g, feq)
+        assert abs(oracle.dH_mirror(g, feq, a)) < 1e-16
+        lim = 2 + np.sum(g * x ** 3) / (3 * np.sum(g * x ** 2))
+        r = abs(a - lim) / eps ** 2
+        if prev is not None:
+            assert r < 2.0 * prev + 1.0  # residual/eps^2 stays bounded
+        prev = r
+    assert abs(a - 2) < 0.01
+
+
+# --------------------------------------------------------------------------
+# Path-length coefficients against independent quadrature constructions
+# (App. B: Gauss-Legendre and Newton-Cotes integrals of 1/(1+z) on [0, y])
+# --------------------------------------------------------------------------
+def _gauss_legendre(y, n):
+    t, wt = np.polynomial.legendre.leggauss(n)
+    z = 0.5 * y * (t + 1)
+    return 0.5 * y * np.sum(wt / (1 + z))
+
+
+def _boole(y):
+    z = np.array([0, 0.25, 0.5, 0.75, 1.0]) * y
+    return y / 90.0 * np.sum(np.array([7, 32, 12, 32, 7]) / (1 + z))
+
+
+def _ungated_state(D, rng, eps=0.05):
+    while True:
+        g, feq = perturbed_state(D, eps, rng)
+        if np.max(np.abs(feq / g - 1)) > 2e-3 and np.all(g > 0):
+            return g, feq
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_coefficients_match_quadratures(D):
+    """c1 = <f, x I_GL1(x)>, c = <f, x I_GL3(x)> (App. B) and, at beta = 1, the
+    Omega+ part of b is <f, ((1+y) I_NC4(y) - y)> / alpha_L^2, y = alpha_L x
+    (Boole's rule: the reading of the undefined I_NC3 as I_NC4)."""
+    rng = np.random.default_rng(20 + D)
+    for _ in range(20):
+        g, feq = _ungated_state(D, rng)
+        x = feq / g - 1
+        det = oracle.path_length(g, feq, 1.0, "higher")
+        assert not det["gated"]
+        c1 = sum(gi * xi * _gauss_legendre(xi, 1) for gi, xi in zip(g, x))
+        c = sum(gi * xi * _gauss_legendre(xi, 3) for gi, xi in zip(g, x))
+        assert abs(det["c1"] - c1) < 1e-14 * max(1.0, abs(c1)) + 1e-17
+        assert abs(det["c"] - c) < 1e-13 * abs(c) + 1e-17
+        aL = det["alpha_lower"]
+        neg = x < 0
+        b = np.sum(g[neg] * x[neg] ** 2 / 2)
+        for gi, xi in zip(g[~neg], x[~neg]):
+            y = aL * xi
+            b += gi * ((1 + y) * _boole(y) - y) / aL ** 2
+        assert abs(det["b"] - b) < 1e-12 * abs(b)
+        # b's Omega+ correction scales with beta^2
+        for beta in (0.5, 0.9):
+            dbeta = oracle.path_length(g, feq, beta, "higher")
+            assert abs((det["b1"] - dbeta["b"]) - beta ** 2 * (det["b1"] - det["b"])) < 1e-13 * abs(det["b"])
+        # alpha_Lower coefficients: a1 = <f,x^3/2>_-, b1 = <f,x^2/2>
+        assert abs(det["a1"] - np.sum(g[neg] * x[neg] ** 3) / 2) < 1e-15
+        assert abs(det["b1"] - np.sum(g * x * x) / 2) < 1e-15
+
+
+def _sextic(alpha, g, x, beta):
+    """Eq. sexticPolynomial (App. C), typed from the paper."""
+    neg = x < 0
+    ab = alpha * beta
+    xm = x[neg]
+    t1 = -np.sum(g[neg] * (ab ** 2 * xm ** 3 / 6 - ab ** 3 * xm ** 4 / 12 + ab ** 4 * xm ** 5 / 20
+                           - ab ** 5 * xm ** 6 / 5))
+    t2 = np.sum(g * ab * x * x / 2)
+    xp = x[~neg]
+    t3 = -np.sum(g[~neg] * 2 * ab ** 2 * xp ** 3 / 15 * (2 / (4 + ab * xp) + 1 / (4 + 2 * ab * xp)
+                                                       + 2 / (4 + 3 * ab * xp)))
+    t4 = -np.sum(g * (60 * x ** 2 + 60 * x ** 3 + 11 * x ** 4) / (60 + 90 * x + 36 * x ** 2 + 3 * x ** 3))
+    return t1 + t2 + t3 + t4
+
+
+def _quintic(alpha, g, x, beta, aL):
+    """Eq. quinticPolynomial (App. C), typed from the paper."""
+    neg = x < 0
+    xm = x[neg]
+    t1 = -alpha ** 2 * beta ** 2 * np.sum(g[neg] * (xm ** 3 / 6 - alpha * beta * xm ** 4 / 12
+                                                    + alpha ** 2 * beta ** 2 * xm ** 5 / 20
+                                                    - alpha ** 3 * beta ** 3 * xm ** 6 / 5))
+    xp = x[~neg]
+    bb = np.sum(g * x * x / 2) - np.sum(g[~neg] * 2 * aL * beta ** 2 * xp ** 3 / 15 * (
+        2 / (4 + aL * xp) + 1 / (4 + 2 * aL * xp) + 2 / (4 + 3 * aL * xp)))
+    t3 = -np.sum(g * (60 * x ** 2 + 60 * x ** 3 + 11 * x ** 4) / (60 + 90 * x + 36 * x ** 2 + 3 * x ** 3))
+    return t1 + alpha * bb + t3
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_quadratic_quintic_sextic_chain(D):
+    """App. C: the quadratic H(alpha) = -a alpha^2 + b alpha - c equals the quintic
+    at alpha = h (the h split vanishes), the quintic equals the sextic at
+    alpha = alpha_L when beta = 1 (the alpha_L split vanishes), and the roots are
+    ordered alpha_L <= alpha_H <= h with the sextic non-positive at alpha_H."""
+    rng = np.random.default_rng(30 + D)
+    for _ in range(30):
+        g, feq = _ungated_state(D, rng, eps=0.08)
+        x = feq / g - 1
+        for beta in (1.0, 0.97, 0.8):
+            det = oracle.path_length(g, feq, beta, "higher")
+            a, b, c, h, aL = det["a"], det["b"], det["c"], det["h"], det["alpha_lower"]
+            quad = lambda s: -a * s * s + b * s - c
+            scale = abs(c) + 1e-300
+            assert abs(quad(h) - _quintic(h, g, x, beta, aL)) < 1e-11 * scale
+            if beta == 1.0:
+                assert abs(_quintic(aL, g, x, beta, aL) - _sextic(aL, g, x, beta)) < 1e-11 * scale
+            aH = det["alpha_unguarded"]
+            assert abs(quad(aH)) < 1e-12 * scale
+            assert abs(-det["a2"] * h * h + b * h - c) < 1e-12 * scale  # H2(h) = 0
+            # |a| >= |a2| always, so alpha_H <= h; alpha_L <= alpha_H is the
+            # assumption of the alpha_L split and is checked where that split
+            # is exact (beta = 1): alpha_L does not depend on beta, alpha_H does.
+            assert aH <= h * (1 + 1e-12)
+            # (far from equilibrium, where the mirror state of ELBM does not
+            # exist, alpha_L can exceed alpha_H: such states are skipped)
+            if beta == 1.0 and np.isfinite(oracle.alpha_elbm(g, feq)):
+                assert aL <= aH * (1 + 1e-12)
+            assert _sextic(aH, g, x, beta) <= 1e-12 * scale
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_alpha_lower_in_unit_interval_and_root(D):
+    """alpha_L in (0, 2) and H1(alpha_L) = 0 (Eq. dissipativescheme)."""
+    rng = np.random.default_rng(40 + D)
+    for _ in range(50):
+        g, feq = _ungated_state(D, rng, eps=0.1)
+        det = oracle.path_length(g, feq, 0.9, "lower")
+        aL = det["alpha_lower"]
+        assert 0 < aL < 2
+        res = -det["a1"] * aL ** 2 + det["b1"] * aL - det["c1"]
+        assert abs(res) < 1e-12 * det["c1"]
+        assert det["alpha_unguarded"] == aL
+
+
+@pytest.mark.parametrize("which", ["lower", "higher"])
+def test_path_length_limits(which):
+    """Small-departure limits: Eq. limitalpha for alpha_L and Eq. alphahigherlimit
+    for alpha_H; the residual shrinks like eps^2."""
+    rng = np.random.default_rng(50)
+    d = null_space_direction(3, rng)
+    beta = 0.95
+    ratios = []
+    for eps in (8e-3, 4e-3, 2e-3):
+        g, feq = perturbed_state(3, eps, rng, rho=1.02, u=np.array([0.05, -0.01, 0.02]), direction=d)
+        x = feq / g - 1
+        det = oracle.path_length(g, feq, beta, which)
+        assert not det["gated"]
+        m2 = np.sum(g * x ** 2)
+        if which == "lower":
+            lim = 2 - np.sum(g[x >= 0] * x[x >= 0] ** 3) / m2 + 3 * np.sum(g[x < 0] * x[x < 0] ** 3) / m2
+            got = det["alpha_lower"]
+        else:
+            lim = 2 + (4 * beta ** 2 / 3 - 1) * np.sum(g * x ** 3) / m2
+            got = det["alpha"]
+        ratios.append(abs(got - lim) / np.max(np.abs(x)) ** 2)
+    assert ratios[-1] < 1.5 * ratios[0] + 1e-3
+    assert max(ratios) < 50
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_h_theorem_per_cell(D):
+    """The exact entropy change of the collision at alpha_H is <= 0
+    (Eq. deltaH3 with log1p), also far from equilibrium; same for alpha_L."""
+    rng = np.random.default_rng(60 + D)
+    viol = 0
+    for k in range(1500):
+        eps = [0.01, 0.05, 0.2][k % 3]
+        g, feq = perturbed_state(D, eps, rng)
+        if np.any(g <= 0):
+            continue
+        beta = [0.5, 0.9, 0.99, 0.9999][k % 4]
+        for mode in ("higher", "lower"):
+            det = oracle.path_length(g, feq, beta, mode)
+            if det["gated"]:
+                continue
+            dh = oracle.dH_step(g, feq, det["alpha"], beta)
+            viol += dh > 1e-15 * np.sum(g)
+    assert viol == 0
+
+
+def test_alpha_higher_close_to_elbm():
+    """|alpha_H - alpha_ELBM| = O(eps^2) as beta -> 1 (Sec. V C: insignificant)."""
+    rng = np.random.default_rng(70)
+    d = null_space_direction(2, rng)
+    prev = None
+    for eps in (6e-3, 3e-3, 1.5e-3):
+        g, feq = perturbed_state(2, eps, rng, rho=1.0, u=np.array([0.04, 0.02]), direction=d)
+        det = oracle.path_length(g, feq, 1 - 1e-4, "higher")
+        ae = oracle.alpha_elbm(g, feq)
+        diff = abs(det["alpha"] - ae)
+        xm = np.max(np.abs(feq / g - 1))
+        assert diff < 10 * xm ** 2
+        prev = diff
+    assert prev < 1e-4
+
+
+def test_iterate1_closer_than_lower():
+    """alpha_Iterate1 (one Newton step from alpha_L) is much closer to alpha_ELBM
+    than alpha_L (Sec. V C)."""
+    rng = np.random.default_rng(71)
+    for _ in range(20):
+        g, feq = _ungated_state(2, rng, eps=0.03)
+        ae = oracle.alpha_elbm(g, feq)
+        if not np.isfinite(ae):
+            continue
+        aL = oracle.path_length(g, feq, 1.0, "lower")["alpha_lower"]
+        a1 = oracle.alpha_iterate1(g, feq)
+        # a Newton step: the error contracts quadratically
+        assert abs(a1 - ae) < 0.5 * abs(aL - ae)
+        assert abs(a1 - ae) < 2.0 * (aL - ae) ** 2 + 1e-12
+
+
+# --------------------------------------------------------------------------
+# Gate and guard (App. D)
+# --------------------------------------------------------------------------
+_CONST = {r[0]: float(r[1]) for r in _golden("gate_guard.txt")}
+
+
+def test_golden_constants():
+    _, w = oracle.lattice(1)
+    assert w[1] == _CONST["w0"] and w[0] == w[2] == _CONST["w1"]
+
+
+def test_gate_threshold():
+    assert _CONST["gate"] == 1e-3
+    rng = np.random.default_rng(80)
+    d = null_space_direction(2, rng)
+    feq = oracle.equilibrium(2, 1.0, [0.02, 0.01])
+    # scale the perturbation so max|x| straddles 1e-3
+    for target, gated in ((0.99e-3, True), (1.01e-3, False)):
+        lo, hi = 0.0, 1e-2
+        for _ in range(200):
+            mid = 0.5 * (lo + hi)
+            g = feq + mid * d * feq.max()
+            if np.max(np.abs(feq / g - 1)) < target:
+                lo = mid
+            else:
+                hi = mid
+        g = feq + lo * d * feq.max()
+        det = oracle.path_length(g, feq, 0.99, "higher")
+        assert det["gated"] == gated
+        if gated:
+            assert det["alpha"] == 2.0
+
+
+def test_equilibrium_input_is_fixed_point():
+    """f = f^eq collides to itself with alpha = 2 (1x1 periodic grid: streaming
+    maps the cell onto itself, so one step is a pure collision)."""
+    for D in (2, 3):
+        feq = oracle.equilibrium(D, 1.1, [0.04, -0.03, 0.02][:D])
+        f = feq.reshape((-1,) + (1,) * D)
+        out, alpha, (ng, nd) = oracle.step(f, 1, 0.01, want_alpha=True)
+        np.testing.assert_allclose(out.ravel(), feq, rtol=1e-15, atol=0)
+        assert alpha.ravel()[0] == 2.0 and ng == 1 and nd == 0
+
+
+def test_guard_keeps_populations_positive():
+    """A population far above its equilibrium (x_min near -1) makes
+    alpha_H exceed alpha_max = -1/(beta x_min); the guard sets
+    alpha = (1 + alpha_max)/2 and the post-collision state stays positive."""
+    D = 2
+    feq = oracle.equilibrium(D, 1.0, [0.0, 0.0])
+    g = feq.copy()
+    g[0] += 0.2        # x_0 = feq0/g0 - 1 close to -1
+    g[8] += 0.2        # (c0 = -c8 keeps the momentum at zero)
+    g[4] -= 0.4        # rest population well below its equilibrium
+    assert np.all(g > 0)
+    rho, u = oracle.cell_moments(D, g)
+    feq = oracle.equilibrium(D, rho, u)
+    beta = 0.9999
+    det = oracle.path_length(g, feq, beta, "higher")
+    assert not det["gated"]
+    x = feq / g - 1
+    amax = -1 / (beta * x.min())
+    assert det["alpha_unguarded"] > amax
+    assert det["guarded"]
+    assert abs(det["alpha"] - (1 + amax) / 2) < 1e-15
+    post = g + det["alpha"] * beta * (feq - g)
+    assert np.all(post > 0)
+    # without the guard the state would leave the polytope of positivity
+    assert np.any(g + det["alpha_unguarded"] * beta * (feq - g) < 0)
+
+
+def test_nonpositive_input_raises():
+    f = oracle.equilibrium(2, 1.0, [0.0, 0.0]).reshape(9, 1, 1).copy()
+    f[3] = -1e-3
+    with pytest.raises(oracle.OracleError):
+        oracle.step(f, 1, 0.01)
+    f[3] = np.nan
+    with pytest.raises(oracle.OracleError):
+        oracle.step(f, 1, 0.01)
+
+
+# --------------------------------------------------------------------------
+# Whole-lattice step: streaming, conservation, H, viscosity
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("D", [2, 3])
+def test_streaming_is_pull_permutation(D):
+    """With beta -> 0 the step is pure free flight (Eq. advection):
+    f_i(x + c_i, t + 1) = f_i(x, t), i.e. np.roll of each population by c_i."""
+    rng = np.random.default_rng(90 + D)
+    shape = (5, 7) if D == 2 else (3, 4, 5)
+    c, w = oracle.lattice(D)
+    f = (w.reshape((-1,) + (1,) * D) * (1 + 0.1 * rng.random((len(w),) + shape)))
+    out = oracle.step(f, 1, 1e30)
+    for i in range(len(w)):
+        shift = tuple(int(c[i, a]) for a in reversed(range(D)))  # array axes are (z,) y, x
+        np.testing.assert_array_equal(out[i], np.roll(f[i], shift, axis=tuple(range(D))))
+
+
+@pytest.mark.parametrize("mode", ["higher", "lower", "bgk"])
+def test_mass_momentum_conserved_and_H_nonincreasing(mode):
+    from paper_2203_12946_amd import workloads as W
+    rho, u = W.taylor_green_3d(12, u0=0.1, noise=2e-2, seed=9)
+    f = oracle.init_equilibrium(rho, u)
+    c, _ = oracle.lattice(3)
+    m0 = f.sum()
+    mom = lambda s: s.reshape(len(c), -1).sum(1) @ c.astype(float)
+    p0 = mom(f)
+    Hprev = oracle.H(f)
+    for _ in range(6):
+        f = oracle.step(f, 2, 2e-3, mode=mode)
+        assert abs(f.sum() - m0) < 1e-12 * m0
+        np.testing.assert_allclose(mom(f), p0, atol=1e-13)
+        Hn = oracle.H(f)
+        if mode != "bgk":
+            assert Hn <= Hprev + 1e-12 * abs(Hprev)
+        Hprev = Hn
+
+
+def test_taylor_green_2d_viscous_decay():
+    """64x64 D2Q9 Taylor-Green, nu = 0.01: KE(t) ~ exp(-4 nu k^2 t),
+    KE(1000)/KE(0) = exp(-0.3855) ~ 0.680 (viscosity nu = tau theta0)."""
+    from paper_2203_12946_amd import workloads as W
+    rho, u = W.taylor_green_2d(64)
+    f = oracle.init_equilibrium(rho, u)
+    nu = 0.01
+    k = 2 * math.pi / 64
+
+    def ke(state):
+        r, v = oracle.moments(state)
+        return 0.5 * np.sum(r * (v ** 2).sum(0))
+
+    k0 = ke(f)
+    f1 = oracle.step(f, 200, W.tau_from_nu(nu))
+    f2 = oracle.step(f1, 800, W.tau_from_nu(nu))
+    rate = -math.log(ke(f2) / ke(f1)) / 800
+    assert abs(rate / (4 * nu * k * k) - 1) < 0.02
+    assert abs(ke(f2) / k0 - math.exp(-4 * nu * k * k * 1000)) < 0.01
+
+
+def test_light_cone_block_reproduces_full_grid():
+    """The sampled-parity harness: k oracle steps on a (2k+1)^D periodic block
+    give the centre cell of the full-grid run exactly."""
+    from paper_2203_12946_amd import workloads as W
+    rho, u = W.shear_layer(48)
+    f = oracle.init_equilibrium(rho, u)
+    k = 4
+    full = oracle.step(f, k, 3e-5)
+    for center in ((0, 0), (12, 30), (47, 5)):
+        blk = oracle.light_cone_block(f, center, k)
+        out = oracle.step(blk, k, 3e-5)
+        np.testing.assert_array_equal(out[:, k, k], full[:, center[0], center[1]])
