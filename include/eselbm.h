@@ -1,0 +1,206 @@
+/*
+ * eselbm.h -- C ABI of the MI355X (gfx950) essentially entropic lattice
+ * Boltzmann library.
+ *
+ * The library implements one time step of the essentially entropic lattice
+ * Boltzmann model (ESELBM) of Atif, Kolluru, Ansumali, arXiv:2203.12946:
+ * pull-streaming (free flight, Sec. II, Eq. advection) followed by the
+ * entropic collision f* = f + alpha beta (f^eq - f) (Sec. II, Eq. fstar_def)
+ * with the product-form entropic equilibrium (Sec. II) and the closed-form
+ * path length alpha_Higher (Sec. IV B, Eq. qaud_tight / qaud_tight_coeff,
+ * App. C), gated to alpha = 2 near equilibrium and guarded for positivity
+ * (App. D).  It also provides the exact adjoint (vector-Jacobian product) of
+ * that step.  The paper has no adjoint: it is an addition of this library.
+ *
+ * Conventions
+ * -----------
+ * Lattices are the D1Q3 tensor products D2Q9 and D3Q27, with
+ * population index i = sum_a (c_ia + 1) 3^a, x axis fastest.  So
+ * opposite(i) = Q-1-i and the rest population is (Q-1)/2.
+ *
+ * State layout: structure of arrays f[i][z][y][x], x fastest, contiguous,
+ * nz = 1 for D2Q9.  A state holds post-collision populations.  The grid is
+ * periodic on every axis.
+ *
+ * Storage types:
+ *   ESELBM_F64          double populations, double arithmetic.
+ *   ESELBM_F32          float populations, float arithmetic.
+ *   ESELBM_F16_SHIFTED  _Float16 deviations f_i - w_i (rho0 = 1), float
+ *                       arithmetic.
+ * Accumulated diagnostics are always double.  The "compute type" below is
+ * double for ESELBM_F64 and float otherwise.
+ *
+ * tau is the paper's relaxation time: beta = 1 / (2 tau + 1) and
+ * nu = tau / 3 (Sec. II).  It must be > 0.
+ *
+ * Ownership: every buffer passed in is device memory owned by the caller.
+ * The library never frees caller memory.  It owns only the handle and a
+ * small (< 4 KiB) device block of diagnostic accumulators, which
+ * eselbm_create allocates and eselbm_destroy frees.
+ *
+ * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
+ * stream.  All kernels are enqueued on it asynchronously.  Only
+ * eselbm_alpha_stats synchronises (that stream only).
+ *
+ * Errors: every entry point returns an eselbm_status.  Nothing aborts or
+ * throws across the ABI.  Argument errors are detected before anything is
+ * enqueued.  Kernel faults surface as ESELBM_E_HIP at the next synchronising
+ * call.  eselbm_last_error() returns a thread-local message for the last
+ * failure.
+ *
+ * Thread safety: a handle may be used by one host thread at a time.  Calls
+ * on different handles are independent.
+ */
+#ifndef ESELBM_H
+#define ESELBM_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct eselbm_ctx *eselbm_handle;
+
+typedef enum { ESELBM_D2Q9 = 0, ESELBM_D3Q27 = 1 } eselbm_lattice;
+typedef enum { ESELBM_F64 = 0, ESELBM_F32 = 1, ESELBM_F16_SHIFTED = 2 } eselbm_dtype;
+/* HIGHER: alpha_Higher (Sec. IV B, App. D), the default.
+ * BGK:    alpha = 2 everywhere, no gate or guard (standard LBGK, Sec. II).
+ * LOWER:  alpha_Lower (Sec. IV A, Eq. alphaLowerSoln) with the same gate
+ *         and guard. */
+typedef enum { ESELBM_MODE_HIGHER = 0, ESELBM_MODE_BGK = 1, ESELBM_MODE_LOWER = 2 } eselbm_mode;
+typedef enum {
+    ESELBM_OK = 0,
+    ESELBM_E_ARG = 1,          /* invalid argument; nothing was enqueued */
+    ESELBM_E_UNSUPPORTED = 2,  /* valid but unsupported combination */
+    ESELBM_E_HIP = 3,          /* a HIP runtime call failed */
+    ESELBM_E_NONPOSITIVE = 4   /* a pre-collision population was <= 0 or not finite */
+} eselbm_status;
+
+/* Diagnostics of the last step run with statistics enabled.  Sums are over
+ * the pre-collision moments of every cell (equal to the post-collision
+ * ones, Sec. II: collisions conserve rho and rho u).
+ *
+ *   mass      sum rho
+ *   mom[a]    sum rho u_a
+ *   kinetic   sum rho |u|^2 / 2
+ *   H         sum <f, log(f/w) - 1> of the step's output state (Eq. hdef),
+ *             only when requested (it is a separate pass), else 0.
+ *   alpha_*   statistics of the path length over cells that collided.
+ *   n_gated   cells with max|x_i| < 1e-3, hence alpha = 2 (App. D).
+ *   n_guard   cells where the positivity guard fired (App. D).
+ *   n_nonpos  cells with a pre-collision population <= 0 or not finite.
+ *             Those cells are streamed but not collided: they keep their
+ *             pulled populations.
+ *   n_alpha_lt2  cells with alpha < 2.
+ *   n_exact   cells whose path length was evaluated with the exact rational
+ *             sums (single precision evaluates cells with all |x_i| < 0.02
+ *             through truncated power series of the same sums; double
+ *             precision always uses the exact sums).
+ */
+typedef struct {
+    double mass, mom[3], kinetic, H;
+    double alpha_min, alpha_max, alpha_mean;
+    long long n_cells, n_gated, n_guard, n_nonpos, n_alpha_lt2, n_exact;
+} eselbm_stats;
+
+/* Creates a solver for an nx * ny * nz periodic grid (nz must be 1 for
+ * D2Q9).  Allocates the < 4 KiB accumulator block on the current device.
+ * Errors: ESELBM_E_ARG for a NULL out, dims < 1, unknown lattice or dtype,
+ * or a grid whose state does not fit a 63-bit index. */
+eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int nz, int dtype);
+
+/* Frees the handle and its accumulator block.  NULL is accepted. */
+eselbm_status eselbm_destroy(eselbm_handle h);
+
+/* Selects the path-length rule (eselbm_mode). */
+eselbm_status eselbm_set_mode(eselbm_handle h, int mode);
+
+/* Enables (1) or disables (0) the fused diagnostic reduction in later
+ * eselbm_step calls.  Only the last step of a call accumulates.  Off by
+ * default: benchmarks run with it off. */
+eselbm_status eselbm_set_stats(eselbm_handle h, int enable);
+
+/* Registers a device buffer of n_cells compute-type values that receives
+ * the per-cell alpha of the last step of each eselbm_step call.  NULL
+ * disables it.  Cells that were not collided receive NaN.  Debug and
+ * parity use only. */
+eselbm_status eselbm_set_alpha_field(eselbm_handle h, void *alpha);
+
+/* Registers a body-force density F (device float, [D][nz][ny][nx]) added
+ * after the collision as f* += feq(rho, u + F/rho) - feq(rho, u) (exact
+ * difference), or NULL for none.  The paper has no forcing: this term and
+ * its form are this library's choice.  Supported for ESELBM_F32 only. */
+eselbm_status eselbm_set_force(eselbm_handle h, const float *F);
+
+/* f = feq(rho, u) in every cell, i.e. an equilibrium initial state.
+ * rho: device double [nz][ny][nx].  u: device double [D][nz][ny][nx].
+ * f: device state in the handle's storage type. */
+eselbm_status eselbm_init_equilibrium(eselbm_handle h, const double *rho, const double *u,
+                                      void *f, void *stream);
+
+/* Runs nsteps >= 1 pull-stream + collide steps.
+ * f_in holds the initial state; the result is in f_out.  For nsteps > 1,
+ * f_in is the ping-pong partner and is overwritten.  f_in and f_out must
+ * be distinct, non-overlapping buffers of Q * n_cells storage elements.
+ * With statistics enabled, the last step fills the accumulators. */
+eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, double tau,
+                          void *stream);
+
+/* Synchronises `stream` and copies out the diagnostics of the last
+ * statistics-enabled step.  with_H != 0 first runs the H pass on that
+ * step's output state (which must still hold it).  Returns
+ * ESELBM_E_NONPOSITIVE if n_nonpos > 0.  The struct is filled in that case
+ * too.  Returns ESELBM_E_ARG if no statistics-enabled step ran since
+ * create. */
+eselbm_status eselbm_alpha_stats(eselbm_handle h, eselbm_stats *out, int with_H, void *stream);
+
+/* Density and velocity fields of a state, computed in double.
+ * rho: device double [cells]; u: device double [D][cells].  With a force
+ * registered, u includes the F/(2 rho) half-force shift. */
+eselbm_status eselbm_moments(eselbm_handle h, const void *f, double *rho, double *u, void *stream);
+
+/* Adjoint of one step (not in the paper; the exact vector-Jacobian
+ * product of the discrete map, derivatives taken through alpha, h,
+ * alpha_Lower and the quadratics' roots, with the Omega+-/Omega- membership
+ * of each population held fixed, d alpha = 0 in gated cells, and the guard
+ * differentiated through x_min).
+ *   f_n:      state at step n (storage type), the input of the step.
+ *   lam_next: adjoint of the state at step n+1 (compute type, Q * cells).
+ *   lam_n:    receives the adjoint of the state at step n (compute type).
+ *             Must not alias lam_next.
+ *   force_grad: NULL, or with a force registered, a device float
+ *             [D][cells] buffer to which dL/dF of this step is ADDED.
+ * Supported for ESELBM_F32 and ESELBM_F64 in modes HIGHER, LOWER and BGK. */
+eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next,
+                                  void *lam_n, double tau, void *force_grad, void *stream);
+
+/* Kinetic-energy loss and its seed (not in the paper):
+ * L = sum_x rho |u|^2 / 2 of state f.  The value is ADDED to *loss_dev (a
+ * device double).  lam (compute type, Q * cells) is overwritten with
+ * scale * dL/df.  Either output may be NULL. */
+eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
+                                  double scale, void *stream);
+
+/* Dissipation loss term of one state and its seed (not in the paper):
+ * L = weight * sum_x |omega(x)|^2 with omega the vorticity from periodic
+ * second-order central differences of u (u includes the half-force
+ * shift when a force is registered).  The value is ADDED to *loss_dev.
+ * weight * dL/df is ADDED to lam (compute type).  Either output may be
+ * NULL. */
+eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
+                                      double weight, void *stream);
+
+/* Adjoint of eselbm_init_equilibrium with respect to u (rho held fixed):
+ * grad_u[a][x] = sum_i lam[i][x] d feq_i(rho, u)/d u_a.
+ * rho, u: device double as in init; lam: compute type; grad_u: device
+ * double [D][cells], overwritten. */
+eselbm_status eselbm_equilibrium_vjp(eselbm_handle h, const double *rho, const double *u,
+                                     const void *lam, double *grad_u, void *stream);
+
+/* Thread-local message describing the last failure ("" if none). */
+const char *eselbm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESELBM_H */

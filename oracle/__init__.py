@@ -74,6 +74,8 @@ def _load():
     lib.orc_init_equilibrium.restype = None
     lib.orc_moments.argtypes = [ctypes.c_int, ctypes.c_longlong, dp, dp, dp]
     lib.orc_moments.restype = None
+    lib.orc_num_threads.argtypes = []
+    lib.orc_num_threads.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -241,6 +243,11 @@ def H(f) -> float:
     f = _f64(f)
     D = _grid(f)[0]
     return _load().orc_H(D, f[0].size, _dp(f))
+
+
+def num_threads() -> int:
+    """OpenMP threads the oracle's cell loops use."""
+    return int(_load().orc_num_threads())
 
 
 def beta_of_tau(tau: float) -> float:

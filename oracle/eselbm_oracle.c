@@ -433,3 +433,11 @@ void orc_moments(int D, long long N, const double *f, double *rho, double *u)
         for (int a = 0; a < D; ++a) u[(long long)a * N + n] = uu[a];
     }
 }
+
+/* Threads the OpenMP loops above use (for reporting timings). */
+#ifdef _OPENMP
+#include <omp.h>
+int orc_num_threads(void) { return omp_get_max_threads(); }
+#else
+int orc_num_threads(void) { return 1; }
+#endif

@@ -1,0 +1,167 @@
+"""Differentiable rollouts of the ESELBM step (torch.autograd front end).
+
+Every step, loss and adjoint is a kernel of libeselbm.so; this module only
+schedules them:
+
+* ``Rollout.forward`` runs n steps, keeping the state every ``ckpt_every``
+  steps (checkpoints) and, optionally, accumulating a dissipation loss
+  weight * sum_x |omega|^2 after every step.
+* ``Rollout.backward`` sweeps the checkpoint segments in reverse.  For each
+  segment it recomputes the segment's states from its checkpoint, then applies
+  the adjoint step kernel from the last state down to the first, adding the
+  per-step loss seeds on the way.  The adjoint kernel also accumulates the
+  body-force gradient.
+
+Autograd functions wrap the three pieces of a training objective:
+``equilibrium`` (initial state from rho, u; gradient w.r.t. u), ``rollout``
+(state after n steps and the accumulated dissipation; gradients w.r.t. the
+initial state and the force) and ``kinetic_energy`` (sum rho |u|^2 / 2).
+"""
+from __future__ import annotations
+
+import torch
+
+from .eselbm import Solver
+
+
+class Rollout:
+    def __init__(self, solver: Solver, tau: float, nsteps: int, ckpt_every: int,
+                 diss_weight: float | None = None):
+        if nsteps < 1 or ckpt_every < 1:
+            raise ValueError("nsteps and ckpt_every must be >= 1")
+        self.s = solver
+        self.tau = float(tau)
+        self.nsteps = int(nsteps)
+        self.K = int(ckpt_every)
+        self.diss_weight = diss_weight
+        self.ckpts: dict[int, torch.Tensor] = {}
+
+    def forward(self, f0: torch.Tensor, loss_acc: torch.Tensor | None = None) -> torch.Tensor:
+        """State after nsteps; with a dissipation weight, adds the loss of
+        every state f^1..f^n to ``loss_acc`` (a device float64 scalar)."""
+        s = self.s
+        cur = f0.clone()
+        nxt = s.empty_state()
+        self.ckpts = {0: cur.clone()}
+        for n in range(self.nsteps):
+            s.step(cur, nxt, 1, self.tau)
+            cur, nxt = nxt, cur
+            if self.diss_weight is not None and loss_acc is not None:
+                s.dissipation_loss(cur, loss=loss_acc, weight=self.diss_weight)
+            if (n + 1) % self.K == 0 and (n + 1) < self.nsteps:
+                self.ckpts[n + 1] = cur.clone()
+        return cur
+
+    def backward(self, lam_final: torch.Tensor | None, diss_grad: float = 0.0,
+                 force_grad: torch.Tensor | None = None) -> torch.Tensor:
+        """Adjoint of the initial state given dL/df^n (may be None = 0) and the
+        gradient of the accumulated dissipation loss; accumulates dL/dF."""
+        s = self.s
+        lam = s.empty_adjoint()
+        if lam_final is None:
+            lam.zero_()
+        else:
+            lam.copy_(lam_final)
+        other = s.empty_adjoint()
+        w = None if self.diss_weight is None else self.diss_weight * float(diss_grad)
+        n_end = self.nsteps
+        if w:
+            s.dissipation_loss(self._state_at_end(), lam=lam, weight=w)
+        seg_starts = sorted(self.ckpts)
+        for start in reversed(seg_starts):
+            stop = min(start + self.K, n_end)
+            # states f^start .. f^(stop-1)
+            states = [self.ckpts[start]]
+            for _ in range(start, stop - 1):
+                nxt = s.empty_state()
+                s.step(states[-1], nxt, 1, self.tau)
+                states.append(nxt)
+            for n in range(stop - 1, start - 1, -1):
+                f_n = states[n - start]
+                s.adjoint_step(f_n, lam, other, self.tau, force_grad=force_grad)
+                lam, other = other, lam
+                if w and n >= 1:
+                    s.dissipation_loss(f_n, lam=lam, weight=w)
+            n_end = start
+        return lam
+
+    def _state_at_end(self) -> torch.Tensor:
+        last = max(self.ckpts)
+        cur = self.ckpts[last].clone()
+        nxt = self.s.empty_state()
+        for _ in range(last, self.nsteps):
+            self.s.step(cur, nxt, 1, self.tau)
+            cur, nxt = nxt, cur
+        return cur
+
+
+class _Equilibrium(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, rho, u, solver):
+        ctx.solver = solver
+        ctx.save_for_backward(rho, u)
+        return solver.init_equilibrium(rho.contiguous(), u.contiguous())
+
+    @staticmethod
+    def backward(ctx, gf):
+        rho, u = ctx.saved_tensors
+        s = ctx.solver
+        gu = s.equilibrium_vjp(rho, u, gf.to(s.compute_dtype).contiguous())
+        return None, gu, None
+
+
+class _Rollout(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f0, force, solver, tau, nsteps, ckpt_every, diss_weight):
+        if force is not None:
+            solver.set_force(force.detach().contiguous())
+        ro = Rollout(solver, tau, nsteps, ckpt_every, diss_weight)
+        loss = torch.zeros(1, dtype=torch.float64, device=f0.device)
+        fN = ro.forward(f0.detach().contiguous(), loss if diss_weight is not None else None)
+        ctx.ro = ro
+        ctx.has_force = force is not None
+        return fN, loss[0]
+
+    @staticmethod
+    def backward(ctx, g_fN, g_loss):
+        ro = ctx.ro
+        s = ro.s
+        fg = None
+        if ctx.has_force:
+            fg = torch.zeros((s.D,) + s.shape, dtype=torch.float32, device=s.device)
+        lamN = None if g_fN is None else g_fN.to(s.compute_dtype).contiguous()
+        dl = 0.0 if g_loss is None else float(g_loss)
+        lam0 = ro.backward(lamN, diss_grad=dl, force_grad=fg)
+        return lam0, fg, None, None, None, None, None
+
+
+class _Kinetic(torch.autograd.Function):
+    @staticmethod
+    def forward(ctx, f, solver):
+        ctx.solver = solver
+        ctx.save_for_backward(f)
+        loss = torch.zeros(1, dtype=torch.float64, device=f.device)
+        solver.kinetic_loss(f.detach().contiguous(), loss=loss)
+        return loss[0]
+
+    @staticmethod
+    def backward(ctx, g):
+        (f,) = ctx.saved_tensors
+        s = ctx.solver
+        lam = s.empty_adjoint()
+        s.kinetic_loss(f.contiguous(), lam=lam, scale=float(g))
+        return lam, None
+
+
+def equilibrium(solver: Solver, rho: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    return _Equilibrium.apply(rho, u, solver)
+
+
+def rollout(solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
+            force: torch.Tensor | None = None, diss_weight: float | None = None):
+    """(state after nsteps, accumulated dissipation loss)."""
+    return _Rollout.apply(f0, force, solver, tau, nsteps, ckpt_every, diss_weight)
+
+
+def kinetic_energy(solver: Solver, f: torch.Tensor) -> torch.Tensor:
+    return _Kinetic.apply(f, solver)

@@ -1,0 +1,276 @@
+// Host side of the C ABI declared in include/eselbm.h: argument checks,
+// the handle, the step loop and the diagnostic read-back.  No kernel work
+// happens here; every computation is a kernel enqueued on the caller's
+// stream.
+#include "../../include/eselbm.h"
+#include "internal.hpp"
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+using namespace eselbm;
+
+struct eselbm_ctx {
+    Grid g;
+    int dtype;
+    int mode;
+    int stats_on;
+    int have_stats;
+    int device;
+    void *alpha_field;
+    const float *force;
+    const void *last_out;  // output state of the last statistics-enabled step
+    DevStats *dev_stats;   // kStatSlots slots
+};
+
+static thread_local std::string g_err;
+
+static eselbm_status fail(eselbm_status st, const char *msg)
+{
+    g_err = msg;
+    return st;
+}
+
+static eselbm_status hip_fail(hipError_t e, const char *where)
+{
+    g_err = std::string(where) + ": " + hipGetErrorString(e);
+    return ESELBM_E_HIP;
+}
+
+static size_t elem_size(int dtype) { return dtype == ESELBM_F64 ? 8 : (dtype == ESELBM_F32 ? 4 : 2); }
+
+extern "C" {
+
+const char *eselbm_last_error(void) { return g_err.c_str(); }
+
+eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int nz, int dtype)
+{
+    if (!out) return fail(ESELBM_E_ARG, "eselbm_create: out is NULL");
+    *out = nullptr;
+    if (lattice != ESELBM_D2Q9 && lattice != ESELBM_D3Q27) return fail(ESELBM_E_ARG, "eselbm_create: unknown lattice");
+    if (dtype < ESELBM_F64 || dtype > ESELBM_F16_SHIFTED) return fail(ESELBM_E_ARG, "eselbm_create: unknown dtype");
+    if (nx < 1 || ny < 1 || nz < 1) return fail(ESELBM_E_ARG, "eselbm_create: grid dimensions must be >= 1");
+    if (lattice == ESELBM_D2Q9 && nz != 1) return fail(ESELBM_E_ARG, "eselbm_create: D2Q9 needs nz == 1");
+    const int Q = lattice == ESELBM_D2Q9 ? 9 : 27;
+    const long long N = (long long)nx * ny * nz;
+    if (N > (1LL << 40)) return fail(ESELBM_E_ARG, "eselbm_create: grid too large");
+    eselbm_ctx *h = new (std::nothrow) eselbm_ctx;
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_create: out of host memory");
+    std::memset(h, 0, sizeof(*h));
+    h->g = Grid{lattice == ESELBM_D2Q9 ? 2 : 3, Q, nx, ny, nz, N};
+    h->dtype = dtype;
+    h->mode = ESELBM_MODE_HIGHER;
+    hipError_t e = hipGetDevice(&h->device);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "eselbm_create: hipGetDevice");
+    }
+    e = hipMalloc((void **)&h->dev_stats, sizeof(DevStats) * kStatSlots);
+    if (e != hipSuccess) {
+        delete h;
+        return hip_fail(e, "eselbm_create: hipMalloc");
+    }
+    *out = h;
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_destroy(eselbm_handle h)
+{
+    if (!h) return ESELBM_OK;
+    hipError_t e = hipFree(h->dev_stats);
+    delete h;
+    if (e != hipSuccess) return hip_fail(e, "eselbm_destroy: hipFree");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_set_mode(eselbm_handle h, int mode)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_mode: NULL handle");
+    if (mode < ESELBM_MODE_HIGHER || mode > ESELBM_MODE_LOWER) return fail(ESELBM_E_ARG, "eselbm_set_mode: unknown mode");
+    h->mode = mode;
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_set_stats(eselbm_handle h, int enable)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_stats: NULL handle");
+    h->stats_on = enable != 0;
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_set_alpha_field(eselbm_handle h, void *alpha)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_alpha_field: NULL handle");
+    h->alpha_field = alpha;
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_set_force(eselbm_handle h, const float *F)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_force: NULL handle");
+    if (F && h->dtype != ESELBM_F32) return fail(ESELBM_E_UNSUPPORTED, "eselbm_set_force: forcing needs ESELBM_F32");
+    h->force = F;
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_init_equilibrium(eselbm_handle h, const double *rho, const double *u, void *f, void *stream)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_init_equilibrium: NULL handle");
+    if (!rho || !u || !f) return fail(ESELBM_E_ARG, "eselbm_init_equilibrium: NULL buffer");
+    hipError_t e = launch_init_eq(h->dtype, h->g, rho, u, f, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_init_equilibrium: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, double tau, void *stream)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_step: NULL handle");
+    if (!f_in || !f_out) return fail(ESELBM_E_ARG, "eselbm_step: NULL state buffer");
+    if (nsteps < 1) return fail(ESELBM_E_ARG, "eselbm_step: nsteps must be >= 1");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_step: tau must be finite and > 0");
+    const size_t bytes = (size_t)h->g.Q * (size_t)h->g.N * elem_size(h->dtype);
+    const char *a = (const char *)f_in, *b = (const char *)f_out;
+    if (a < b + bytes && b < a + bytes) return fail(ESELBM_E_ARG, "eselbm_step: f_in and f_out overlap");
+    hipStream_t s = (hipStream_t)stream;
+    // Step k reads one buffer and writes the other, starting f_in -> f_out;
+    // after an even count the newest state is back in f_in and one copy
+    // moves it to f_out (f_in is documented as clobbered).
+    void *src = f_in, *dst = f_out;
+    for (int k = 0; k < nsteps; ++k) {
+        const bool last = k == nsteps - 1;
+        StepArgs sa;
+        sa.fin = src;
+        sa.fout = dst;
+        sa.g = h->g;
+        sa.beta = 1.0 / (2.0 * tau + 1.0);
+        sa.force = h->force;
+        sa.alpha_out = last ? h->alpha_field : nullptr;
+        sa.stats = (last && h->stats_on) ? h->dev_stats : nullptr;
+        const bool diag = sa.alpha_out != nullptr || sa.stats != nullptr;
+        if (sa.stats) {
+            hipError_t e = launch_reset_stats(h->dev_stats, s);
+            if (e != hipSuccess) return hip_fail(e, "eselbm_step: reset");
+        }
+        hipError_t e = launch_step(h->dtype, h->mode, diag, sa, s);
+        if (e != hipSuccess) return hip_fail(e, "eselbm_step: launch");
+        void *t = src;
+        src = dst;
+        dst = t;
+    }
+    if (src != f_out) {
+        hipError_t e = hipMemcpyAsync(f_out, src, bytes, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "eselbm_step: copy");
+    }
+    if (h->stats_on) {
+        h->have_stats = 1;
+        h->last_out = f_out;
+    }
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_alpha_stats(eselbm_handle h, eselbm_stats *out, int with_H, void *stream)
+{
+    if (!h || !out) return fail(ESELBM_E_ARG, "eselbm_alpha_stats: NULL argument");
+    if (!h->have_stats) return fail(ESELBM_E_ARG, "eselbm_alpha_stats: no statistics-enabled step has run");
+    hipStream_t s = (hipStream_t)stream;
+    if (with_H) {
+        hipError_t e = launch_H(h->dtype, h->g, h->last_out, h->dev_stats, s);
+        if (e != hipSuccess) return hip_fail(e, "eselbm_alpha_stats: H launch");
+    }
+    DevStats host[kStatSlots];
+    hipError_t e = hipMemcpyAsync(host, h->dev_stats, sizeof(host), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_alpha_stats: read-back");
+    std::memset(out, 0, sizeof(*out));
+    unsigned long long mn = 0x7FF0000000000000ull, mx = 0;
+    double asum = 0.0;
+    for (int k = 0; k < kStatSlots; ++k) {
+        const DevStats &d = host[k];
+        out->mass += d.mass;
+        for (int c = 0; c < 3; ++c) out->mom[c] += d.mom[c];
+        out->kinetic += d.kinetic;
+        out->H += d.H;
+        asum += d.alpha_sum;
+        out->n_cells += (long long)d.n_cells;
+        out->n_gated += (long long)d.n_gated;
+        out->n_guard += (long long)d.n_guard;
+        out->n_nonpos += (long long)d.n_nonpos;
+        out->n_alpha_lt2 += (long long)d.n_lt2;
+        out->n_exact += (long long)d.n_exact;
+        mn = d.alpha_min_bits < mn ? d.alpha_min_bits : mn;
+        mx = d.alpha_max_bits > mx ? d.alpha_max_bits : mx;
+    }
+    if (!with_H) out->H = 0.0;
+    double dmn, dmx;
+    std::memcpy(&dmn, &mn, 8);
+    std::memcpy(&dmx, &mx, 8);
+    out->alpha_min = out->n_cells ? dmn : NAN;
+    out->alpha_max = out->n_cells ? dmx : NAN;
+    out->alpha_mean = out->n_cells ? asum / (double)out->n_cells : NAN;
+    if (out->n_nonpos > 0) return fail(ESELBM_E_NONPOSITIVE, "eselbm_alpha_stats: non-positive populations met");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_moments(eselbm_handle h, const void *f, double *rho, double *u, void *stream)
+{
+    if (!h || !f || !rho || !u) return fail(ESELBM_E_ARG, "eselbm_moments: NULL argument");
+    hipError_t e = launch_moments(h->dtype, h->g, f, h->force, rho, u, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_moments: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next, void *lam_n, double tau,
+                                  void *force_grad, void *stream)
+{
+    if (!h || !f_n || !lam_next || !lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: NULL argument");
+    if (lam_next == lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: lam_n must not alias lam_next");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: tau must be finite and > 0");
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: F16 storage has no adjoint");
+    if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: force_grad without a registered force");
+    AdjArgs a;
+    a.fn = f_n;
+    a.lam_next = lam_next;
+    a.lam_n = lam_n;
+    a.g = h->g;
+    a.beta = 1.0 / (2.0 * tau + 1.0);
+    a.force = h->force;
+    a.force_grad = (float *)force_grad;
+    hipError_t e = launch_adjoint(h->dtype, h->mode, a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_adjoint_step: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam, double scale,
+                                  void *stream)
+{
+    if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_kinetic_loss: NULL argument");
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_kinetic_loss: F16 storage");
+    hipError_t e = launch_kinetic_loss(h->dtype, h->g, f, loss_dev, lam, scale, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_kinetic_loss: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam, double weight,
+                                      void *stream)
+{
+    if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: NULL argument");
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: F16 storage");
+    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, loss_dev, lam, weight, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_loss: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_equilibrium_vjp(eselbm_handle h, const double *rho, const double *u, const void *lam,
+                                     double *grad_u, void *stream)
+{
+    if (!h || !rho || !u || !lam || !grad_u) return fail(ESELBM_E_ARG, "eselbm_equilibrium_vjp: NULL argument");
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_equilibrium_vjp: F16 storage");
+    hipError_t e = launch_equilibrium_vjp(h->dtype, h->g, rho, u, lam, grad_u, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_equilibrium_vjp: launch");
+    return ESELBM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,443 @@
+// Forward kernels: the fused pull-stream + entropic collision step, the
+// equilibrium initialiser, and the double-precision diagnostics (moments,
+// H function, fused step statistics).
+//
+// Mapping: one lattice cell per lane.  A block is 64..256 lanes along one
+// x-row; blockIdx.x enumerates (x-block, y, z).  Each lane pulls its Q
+// populations from the neighbouring rows (Eq. advection): every population
+// load of a wave is 64 consecutive elements of one row, shifted by at most
+// one element, so loads stay coalesced; every store is aligned.  Each
+// element of f_in is read exactly once over the whole grid, so there is no
+// reuse for LDS or an XCD-aware block order to capture.
+#include "internal.hpp"
+#include "lattice.hpp"
+
+#include <type_traits>
+
+namespace eselbm {
+
+template <typename V>
+__device__ inline V wave_sum(V v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline unsigned long long wave_min_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(v, o, 64);
+        v = t < v ? t : v;
+    }
+    return v;
+}
+
+__device__ inline unsigned long long wave_max_u64(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long t = __shfl_xor(v, o, 64);
+        v = t > v ? t : v;
+    }
+    return v;
+}
+
+// Per-lane diagnostic contributions, reduced over the block and added to
+// one accumulator slot with one atomic per quantity per block.
+struct LaneStats {
+    double mass = 0, mom[3] = {0, 0, 0}, ke = 0, asum = 0;
+    unsigned long long amin = 0x7FF0000000000000ull, amax = 0;
+    unsigned long long n = 0, gated = 0, guard = 0, nonpos = 0, lt2 = 0, exact = 0;
+};
+
+__device__ inline void block_reduce_stats(LaneStats &s, DevStats *slots)
+{
+    __shared__ double red_d[4][7];
+    __shared__ unsigned long long red_u[4][8];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double v[7] = {s.mass, s.mom[0], s.mom[1], s.mom[2], s.ke, s.asum, 0.0};
+    unsigned long long c[6] = {s.n, s.gated, s.guard, s.nonpos, s.lt2, s.exact};
+#pragma unroll
+    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
+#pragma unroll
+    for (int k = 0; k < 6; ++k) c[k] = wave_sum(c[k]);
+    const unsigned long long mn = wave_min_u64(s.amin), mx = wave_max_u64(s.amax);
+    if (lane == 0) {
+        for (int k = 0; k < 6; ++k) red_d[wid][k] = v[k];
+        for (int k = 0; k < 6; ++k) red_u[wid][k] = c[k];
+        red_u[wid][6] = mn;
+        red_u[wid][7] = mx;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        DevStats *st = slots + (blockIdx.x % kStatSlots);
+        double t[6] = {0, 0, 0, 0, 0, 0};
+        unsigned long long u[6] = {0, 0, 0, 0, 0, 0};
+        unsigned long long tmn = red_u[0][6], tmx = red_u[0][7];
+        for (int w = 0; w < nw; ++w) {
+            for (int k = 0; k < 6; ++k) t[k] += red_d[w][k];
+            for (int k = 0; k < 6; ++k) u[k] += red_u[w][k];
+            tmn = red_u[w][6] < tmn ? red_u[w][6] : tmn;
+            tmx = red_u[w][7] > tmx ? red_u[w][7] : tmx;
+        }
+        atomicAdd(&st->mass, t[0]);
+        atomicAdd(&st->mom[0], t[1]);
+        atomicAdd(&st->mom[1], t[2]);
+        atomicAdd(&st->mom[2], t[3]);
+        atomicAdd(&st->kinetic, t[4]);
+        atomicAdd(&st->alpha_sum, t[5]);
+        atomicAdd(&st->n_cells, u[0]);
+        atomicAdd(&st->n_gated, u[1]);
+        atomicAdd(&st->n_guard, u[2]);
+        atomicAdd(&st->n_nonpos, u[3]);
+        atomicAdd(&st->n_lt2, u[4]);
+        atomicAdd(&st->n_exact, u[5]);
+        atomicMin(&st->alpha_min_bits, tmn);
+        atomicMax(&st->alpha_max_bits, tmx);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused step.
+// ---------------------------------------------------------------------------
+// Occupancy floor: the kernel is a stream of Q loads and Q stores per lane,
+// so it needs several waves per SIMD in flight to cover HBM latency.  The
+// register budget is capped accordingly (4 waves: <= 128 VGPRs).
+template <typename S>
+struct StepOcc {
+    static constexpr int waves = 4;
+};
+template <>
+struct StepOcc<double> {
+    static constexpr int waves = 2;
+};
+
+template <int D, typename S, int MODE, bool DIAG, bool FORCE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepOcc<S>::waves))) void k_step(StepArgs a)
+{
+    using T = typename Storage<S>::T;
+    constexpr int Q = Lat<D>::Q;
+    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
+    const long long N = a.g.N;
+    const int nxb = (nx + (int)blockDim.x - 1) / (int)blockDim.x;
+    const int xb = (int)blockIdx.x % nxb;
+    const int row = (int)blockIdx.x / nxb;
+    const int y = row % ny, z = row / ny;
+    const int x = xb * (int)blockDim.x + (int)threadIdx.x;
+    const S *__restrict__ fin = (const S *)a.fin;
+    S *__restrict__ fout = (S *)a.fout;
+    const T beta = (T)a.beta;
+
+    LaneStats ls;
+    if (x < nx) {
+        // source coordinate of a population with velocity component c is
+        // (coordinate - c) mod n, indexed here by c + 1
+        const unsigned xs[3] = {x + 1 == nx ? 0u : (unsigned)x + 1u, (unsigned)x,
+                                x == 0 ? (unsigned)nx - 1u : (unsigned)x - 1u};
+        const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
+        const int zs[3] = {z + 1 == nz ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
+        const long long row0 = ((long long)z * ny + y) * nx;
+        const long long cell = row0 + x;
+
+        // g: populations, gt = g - w: deviations.  Each population's source
+        // row is block-uniform; only the x offset varies per lane.
+        T g[Q], gt[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1, cx = Lat<D>::c(i, 0) + 1;
+            const S *rowp = fin + ((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
+            const T r = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
+            const T w = T(Lat<D>::w(i));
+            gt[i] = Storage<S>::kShifted ? r : r - w;
+            g[i] = Storage<S>::kShifted ? w + r : r;
+        }
+
+        T drho, j[3];
+        moments_shifted<D, T>(gt, drho, j);
+        T gmin = g[0];
+#pragma unroll
+        for (int i = 1; i < Q; ++i) gmin = fmin_(gmin, g[i]);
+        // NaN in any population propagates into drho; fmin ignores it
+        const bool ok = gmin > T(0) && abs_(drho) < T(1e30);
+        const T rho = T(1) + drho;
+        T alpha = T(0);
+        CellInfo info{0, 0, 0};
+        T dd[Q];
+        T ab = T(0);  // the output is g + ab * dd
+        if (ok) {
+            const T ir = rcp_(rho);
+            T u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : T(0)};
+            T feqt[Q];
+            equilibrium_shifted<D, T>(drho, u, feqt);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) dd[i] = feqt[i] - gt[i];
+            alpha = path_length<D, T, MODE>(g, dd, beta, info);
+            ab = alpha * beta;
+            if (FORCE) {
+                T uf[3] = {u[0], u[1], u[2]};
+#pragma unroll
+                for (int c = 0; c < D; ++c) uf[c] += (T)a.force[(long long)c * N + cell] * ir;
+                T feqf[Q];
+                equilibrium_shifted<D, T>(drho, uf, feqf);
+#pragma unroll
+                for (int i = 0; i < Q; ++i) dd[i] = ab * dd[i] + (feqf[i] - feqt[i]);
+                ab = T(1);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) dd[i] = T(0);
+        }
+        // post-collision population g + alpha beta (feq - g) [+ force term]
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            S *orow = fout + ((long long)i * N + row0);
+            const T v = ab * dd[i] + (Storage<S>::kShifted ? gt[i] : g[i]);
+            *lane_ptr(orow, (unsigned)x) = Storage<S>::from_T(v);
+        }
+
+        if (DIAG) {
+            if (a.alpha_out) ((T *)a.alpha_out)[cell] = ok ? alpha : T(__builtin_nan(""));
+            if (ok) {
+                const double r = 1.0 + (double)drho;
+                ls.mass = r;
+                double jj = 0.0;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    ls.mom[c] = (double)j[c];
+                    jj += (double)j[c] * (double)j[c];
+                }
+                ls.ke = 0.5 * jj / r;
+                ls.asum = (double)alpha;
+                const double ad = (double)alpha;
+                ls.amin = __double_as_longlong(ad);
+                ls.amax = ls.amin;
+                ls.n = 1;
+                ls.gated = info.gated;
+                ls.guard = info.guarded;
+                ls.lt2 = alpha < T(2);
+                ls.exact = info.exact;
+            } else {
+                ls.nonpos = 1;
+            }
+        }
+    }
+    if (DIAG && a.stats) block_reduce_stats(ls, a.stats);
+}
+
+template <int D, typename S, int MODE>
+static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
+{
+    const int bx = block_x(a.g.nx);
+    const long long nblk = (long long)((a.g.nx + bx - 1) / bx) * a.g.ny * a.g.nz;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nblk), block(bx);
+    const bool force = a.force != nullptr;
+    if (force) {
+        if constexpr (std::is_same<S, float>::value) {
+            if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_step<D, S, MODE, false, true>), grid, block, 0, s, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
+    if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, false>), grid, block, 0, s, a);
+    else hipLaunchKernelGGL((k_step<D, S, MODE, false, false>), grid, block, 0, s, a);
+    return hipGetLastError();
+}
+
+template <int D, typename S>
+static hipError_t launch_step_m(int mode, bool diag, const StepArgs &a, hipStream_t s)
+{
+    switch (mode) {
+    case MODE_HIGHER: return launch_step_t<D, S, MODE_HIGHER>(diag, a, s);
+    case MODE_BGK: return launch_step_t<D, S, MODE_BGK>(diag, a, s);
+    case MODE_LOWER: return launch_step_t<D, S, MODE_LOWER>(diag, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int D>
+static hipError_t launch_step_d(int dtype, int mode, bool diag, const StepArgs &a, hipStream_t s)
+{
+    switch (dtype) {
+    case 0: return launch_step_m<D, double>(mode, diag, a, s);
+    case 1: return launch_step_m<D, float>(mode, diag, a, s);
+    case 2: return launch_step_m<D, _Float16>(mode, diag, a, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_step(int dtype, int mode, bool diag, const StepArgs &a, hipStream_t s)
+{
+    return a.g.D == 2 ? launch_step_d<2>(dtype, mode, diag, a, s) : launch_step_d<3>(dtype, mode, diag, a, s);
+}
+
+// ---------------------------------------------------------------------------
+// Statistics reset (a fill kernel rather than a memset, so that the step
+// sequence stays capturable in a graph).
+// ---------------------------------------------------------------------------
+__global__ void k_reset_stats(DevStats *st)
+{
+    const int k = threadIdx.x;
+    if (k < kStatSlots) {
+        DevStats z{};
+        z.alpha_min_bits = 0x7FF0000000000000ull;
+        z.alpha_max_bits = 0;
+        st[k] = z;
+    }
+}
+
+hipError_t launch_reset_stats(DevStats *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, s, st);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Equilibrium initial state from double rho, u fields.
+// ---------------------------------------------------------------------------
+template <int D, typename S>
+__global__ __launch_bounds__(256) void k_init_eq(Grid g, const double *__restrict__ rho,
+                                                 const double *__restrict__ u, S *__restrict__ f)
+{
+    using T = typename Storage<S>::T;
+    constexpr int Q = Lat<D>::Q;
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.N) return;
+    const T drho = (T)(rho[cell] - 1.0);
+    T uu[3] = {(T)u[cell], (T)u[g.N + cell], D == 3 ? (T)u[2 * g.N + cell] : T(0)};
+    T feqt[Q];
+    equilibrium_shifted<D, T>(drho, uu, feqt);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T w = T(Lat<D>::w(i));
+        f[(long long)i * g.N + cell] = Storage<S>::from_T(Storage<S>::kShifted ? feqt[i] : w + feqt[i]);
+    }
+}
+
+template <int D>
+static hipError_t launch_init_eq_d(int dtype, const Grid &g, const double *rho, const double *u, void *f,
+                                   hipStream_t s)
+{
+    const dim3 grid((unsigned)((g.N + 255) / 256)), block(256);
+    switch (dtype) {
+    case 0: hipLaunchKernelGGL((k_init_eq<D, double>), grid, block, 0, s, g, rho, u, (double *)f); break;
+    case 1: hipLaunchKernelGGL((k_init_eq<D, float>), grid, block, 0, s, g, rho, u, (float *)f); break;
+    case 2: hipLaunchKernelGGL((k_init_eq<D, _Float16>), grid, block, 0, s, g, rho, u, (_Float16 *)f); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_init_eq(int dtype, const Grid &g, const double *rho, const double *u, void *f,
+                          hipStream_t s)
+{
+    return g.D == 2 ? launch_init_eq_d<2>(dtype, g, rho, u, f, s) : launch_init_eq_d<3>(dtype, g, rho, u, f, s);
+}
+
+// ---------------------------------------------------------------------------
+// Density and velocity in double (diagnostics, parity).
+// ---------------------------------------------------------------------------
+template <int D, typename S>
+__global__ __launch_bounds__(256) void k_moments(Grid g, const S *__restrict__ f, const float *__restrict__ force,
+                                                 double *__restrict__ rho, double *__restrict__ u)
+{
+    constexpr int Q = Lat<D>::Q;
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (cell >= g.N) return;
+    double dr = 0.0, j[3] = {0, 0, 0};
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const double w = Lat<D>::w(i);
+        const double v = Storage<S>::full(f[(long long)i * g.N + cell], w) - w;
+        dr += v;
+#pragma unroll
+        for (int c = 0; c < D; ++c) j[c] += Lat<D>::c(i, c) * v;
+    }
+    const double r = 1.0 + dr;
+    rho[cell] = r;
+#pragma unroll
+    for (int c = 0; c < D; ++c) {
+        double jc = j[c];
+        if (force) jc += 0.5 * (double)force[(long long)c * g.N + cell];
+        u[(long long)c * g.N + cell] = jc / r;
+    }
+}
+
+template <int D>
+static hipError_t launch_moments_d(int dtype, const Grid &g, const void *f, const float *force, double *rho,
+                                   double *u, hipStream_t s)
+{
+    const dim3 grid((unsigned)((g.N + 255) / 256)), block(256);
+    switch (dtype) {
+    case 0: hipLaunchKernelGGL((k_moments<D, double>), grid, block, 0, s, g, (const double *)f, force, rho, u); break;
+    case 1: hipLaunchKernelGGL((k_moments<D, float>), grid, block, 0, s, g, (const float *)f, force, rho, u); break;
+    case 2: hipLaunchKernelGGL((k_moments<D, _Float16>), grid, block, 0, s, g, (const _Float16 *)f, force, rho, u); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(int dtype, const Grid &g, const void *f, const float *force, double *rho, double *u,
+                          hipStream_t s)
+{
+    return g.D == 2 ? launch_moments_d<2>(dtype, g, f, force, rho, u, s)
+                    : launch_moments_d<3>(dtype, g, f, force, rho, u, s);
+}
+
+// ---------------------------------------------------------------------------
+// H function sum_x <f, log(f/w) - 1> (Eq. hdef), double precision.
+// ---------------------------------------------------------------------------
+template <int D, typename S>
+__global__ __launch_bounds__(256) void k_H(Grid g, const S *__restrict__ f, DevStats *st)
+{
+    constexpr int Q = Lat<D>::Q;
+    __shared__ double part[4];
+    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    double h = 0.0;
+    if (cell < g.N) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const double w = Lat<D>::w(i);
+            const double v = Storage<S>::full(f[(long long)i * g.N + cell], w);
+            h += v * (log(v / w) - 1.0);
+        }
+    }
+    h = wave_sum(h);
+    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = h;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double t = 0.0;
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += part[w];
+        atomicAdd(&st[blockIdx.x % kStatSlots].H, t);
+    }
+}
+
+__global__ void k_zero_H(DevStats *st)
+{
+    if (threadIdx.x < kStatSlots) st[threadIdx.x].H = 0.0;
+}
+
+template <int D>
+static hipError_t launch_H_d(int dtype, const Grid &g, const void *f, DevStats *st, hipStream_t s)
+{
+    const dim3 grid((unsigned)((g.N + 255) / 256)), block(256);
+    hipLaunchKernelGGL(k_zero_H, dim3(1), dim3(64), 0, s, st);
+    switch (dtype) {
+    case 0: hipLaunchKernelGGL((k_H<D, double>), grid, block, 0, s, g, (const double *)f, st); break;
+    case 1: hipLaunchKernelGGL((k_H<D, float>), grid, block, 0, s, g, (const float *)f, st); break;
+    case 2: hipLaunchKernelGGL((k_H<D, _Float16>), grid, block, 0, s, g, (const _Float16 *)f, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_H(int dtype, const Grid &g, const void *f, DevStats *st, hipStream_t s)
+{
+    return g.D == 2 ? launch_H_d<2>(dtype, g, f, st, s) : launch_H_d<3>(dtype, g, f, st, s);
+}
+
+}  // namespace eselbm

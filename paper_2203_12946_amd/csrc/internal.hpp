@@ -1,0 +1,69 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace eselbm {
+
+// Diagnostic accumulators.  Several copies ("slots") spread the block-level
+// atomics of one step over distinct addresses; the host adds the slots.
+struct DevStats {
+    double mass, mom[3], kinetic, alpha_sum, H, pad0;
+    unsigned long long alpha_min_bits, alpha_max_bits;
+    unsigned long long n_cells, n_gated, n_guard, n_nonpos, n_lt2, n_exact;
+};
+static_assert(sizeof(DevStats) == 128, "DevStats is one 128-byte line");
+constexpr int kStatSlots = 32;
+
+struct Grid {
+    int D, Q, nx, ny, nz;
+    long long N;  // cells
+};
+
+struct StepArgs {
+    const void *fin;
+    void *fout;
+    Grid g;
+    double beta;
+    const float *force;  // [D][N] or null
+    void *alpha_out;     // [N] compute type or null
+    DevStats *stats;     // kStatSlots slots or null
+};
+
+// Launchers (return the hipError_t of the launch).
+hipError_t launch_step(int dtype, int mode, bool diag, const StepArgs &a, hipStream_t s);
+hipError_t launch_reset_stats(DevStats *st, hipStream_t s);
+hipError_t launch_init_eq(int dtype, const Grid &g, const double *rho, const double *u, void *f,
+                          hipStream_t s);
+hipError_t launch_moments(int dtype, const Grid &g, const void *f, const float *force, double *rho,
+                          double *u, hipStream_t s);
+hipError_t launch_H(int dtype, const Grid &g, const void *f, DevStats *st, hipStream_t s);
+
+struct AdjArgs {
+    const void *fn;
+    const void *lam_next;
+    void *lam_n;
+    Grid g;
+    double beta;
+    const float *force;
+    float *force_grad;
+};
+hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s);
+hipError_t launch_kinetic_loss(int dtype, const Grid &g, const void *f, double *loss, void *lam,
+                               double scale, hipStream_t s);
+hipError_t launch_dissipation_loss(int dtype, const Grid &g, const void *f, const float *force,
+                                   double *loss, void *lam, double weight, hipStream_t s);
+hipError_t launch_equilibrium_vjp(int dtype, const Grid &g, const double *rho, const double *u,
+                                  const void *lam, double *grad_u, hipStream_t s);
+
+// Block shape along x: 64-lane waves, up to 4 per block, enough to cover nx.
+inline int block_x(int nx)
+{
+    int w = (nx + 63) / 64;
+    if (w > 4) w = 4;
+    return 64 * w;
+}
+
+}  // namespace eselbm

@@ -1,0 +1,236 @@
+"""Python binding of libeselbm.so (the C ABI in include/eselbm.h).
+
+Argument marshalling only: every computation runs in the HIP library.
+PyTorch provides device memory (tensors) and the stream (torch's current
+HIP stream).  If the library is not built this module raises on import;
+there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import pathlib
+
+import torch
+
+_LIB_PATH = pathlib.Path(__file__).resolve().parent / "libeselbm.so"
+
+D2Q9, D3Q27 = 0, 1
+F64, F32, F16_SHIFTED = 0, 1, 2
+MODE_HIGHER, MODE_BGK, MODE_LOWER = 0, 1, 2
+OK, E_ARG, E_UNSUPPORTED, E_HIP, E_NONPOSITIVE = 0, 1, 2, 3, 4
+
+DTYPES = {"f64": F64, "f32": F32, "f16s": F16_SHIFTED}
+MODES = {"higher": MODE_HIGHER, "bgk": MODE_BGK, "lower": MODE_LOWER}
+LATTICES = {"D2Q9": D2Q9, "D3Q27": D3Q27}
+TORCH_STORAGE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float16}
+TORCH_COMPUTE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float32}
+
+
+class EselbmError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"eselbm status {status}: {message}")
+        self.status = status
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("mass", ctypes.c_double), ("mom", ctypes.c_double * 3), ("kinetic", ctypes.c_double),
+        ("H", ctypes.c_double), ("alpha_min", ctypes.c_double), ("alpha_max", ctypes.c_double),
+        ("alpha_mean", ctypes.c_double), ("n_cells", ctypes.c_longlong), ("n_gated", ctypes.c_longlong),
+        ("n_guard", ctypes.c_longlong), ("n_nonpos", ctypes.c_longlong),
+        ("n_alpha_lt2", ctypes.c_longlong), ("n_exact", ctypes.c_longlong),
+    ]
+
+    def as_dict(self) -> dict:
+        d = {k: getattr(self, k) for k, _ in self._fields_}
+        d["mom"] = list(self.mom)
+        return d
+
+
+_vp = ctypes.c_void_p
+_SIGNATURES = {
+    "eselbm_create": [ctypes.POINTER(_vp), ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int],
+    "eselbm_destroy": [_vp],
+    "eselbm_set_mode": [_vp, ctypes.c_int],
+    "eselbm_set_stats": [_vp, ctypes.c_int],
+    "eselbm_set_alpha_field": [_vp, _vp],
+    "eselbm_set_force": [_vp, _vp],
+    "eselbm_init_equilibrium": [_vp, _vp, _vp, _vp, _vp],
+    "eselbm_step": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp],
+    "eselbm_alpha_stats": [_vp, ctypes.POINTER(Stats), ctypes.c_int, _vp],
+    "eselbm_moments": [_vp, _vp, _vp, _vp, _vp],
+    "eselbm_adjoint_step": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "eselbm_kinetic_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
+    "eselbm_dissipation_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
+    "eselbm_equilibrium_vjp": [_vp, _vp, _vp, _vp, _vp, _vp],
+}
+EXPORTS = tuple(_SIGNATURES) + ("eselbm_last_error",)
+
+
+def _load() -> ctypes.CDLL:
+    if not _LIB_PATH.exists():
+        raise ImportError(
+            f"{_LIB_PATH} is not built; run `python -m paper_2203_12946_amd.build` "
+            "(there is no CPU fallback)")
+    lib = ctypes.CDLL(str(_LIB_PATH))
+    for name, argtypes in _SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = argtypes
+        fn.restype = ctypes.c_int
+    lib.eselbm_last_error.argtypes = []
+    lib.eselbm_last_error.restype = ctypes.c_char_p
+    return lib
+
+
+lib = _load()
+
+
+def _check(status: int):
+    if status != OK:
+        raise EselbmError(status, lib.eselbm_last_error().decode())
+
+
+def _dev(t: torch.Tensor | None, dtype=None, numel=None) -> _vp:
+    """Pointer of a contiguous device tensor (or NULL)."""
+    if t is None:
+        return _vp(None)
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"expected {numel} elements, got {t.numel()}")
+    return _vp(t.data_ptr())
+
+
+def _stream(stream=None) -> _vp:
+    s = torch.cuda.current_stream() if stream is None else stream
+    return _vp(s.cuda_stream)
+
+
+class Solver:
+    """One periodic grid: lattice, shape (ny, nx) or (nz, ny, nx), storage dtype.
+
+    State tensors are [Q, *shape] in the storage dtype (float16 holds the
+    shifted deviations f - w).  Adjoint tensors are [Q, *shape] in the
+    compute dtype.
+    """
+
+    def __init__(self, lattice: str, shape, dtype: str = "f32", mode: str = "higher",
+                 device: int | None = None):
+        self.lattice = lattice
+        self.D = 2 if lattice == "D2Q9" else 3
+        self.Q = 9 if self.D == 2 else 27
+        shape = tuple(int(s) for s in shape)
+        if len(shape) != self.D:
+            raise ValueError("shape must be (ny, nx) for D2Q9 and (nz, ny, nx) for D3Q27")
+        self.shape = shape
+        nx, ny, nz = (shape[1], shape[0], 1) if self.D == 2 else (shape[2], shape[1], shape[0])
+        self.nx, self.ny, self.nz = nx, ny, nz
+        self.cells = nx * ny * nz
+        self.dtype_code = DTYPES[dtype]
+        self.storage_dtype = TORCH_STORAGE[self.dtype_code]
+        self.compute_dtype = TORCH_COMPUTE[self.dtype_code]
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
+        self._h = _vp()
+        with torch.cuda.device(self.device):
+            _check(lib.eselbm_create(ctypes.byref(self._h), LATTICES[lattice], nx, ny, nz, self.dtype_code))
+        self._alpha = None
+        self._force = None
+        self.set_mode(mode)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib.eselbm_destroy(h)
+            self._h = _vp()
+
+    # ---- configuration --------------------------------------------------
+    def set_mode(self, mode: str):
+        self.mode = mode
+        _check(lib.eselbm_set_mode(self._h, MODES[mode]))
+
+    def set_stats(self, on: bool):
+        _check(lib.eselbm_set_stats(self._h, int(bool(on))))
+
+    def set_alpha_field(self, alpha: torch.Tensor | None):
+        """Register a [*shape] compute-dtype tensor receiving per-cell alpha."""
+        self._alpha = alpha
+        _check(lib.eselbm_set_alpha_field(self._h, _dev(alpha, self.compute_dtype, self.cells)))
+
+    def set_force(self, F: torch.Tensor | None):
+        """Register a [D, *shape] float32 body-force density (F32 storage only)."""
+        self._force = F
+        _check(lib.eselbm_set_force(self._h, _dev(F, torch.float32, self.D * self.cells)))
+
+    # ---- state ----------------------------------------------------------
+    def empty_state(self) -> torch.Tensor:
+        return torch.empty((self.Q,) + self.shape, dtype=self.storage_dtype, device=self.device)
+
+    def empty_adjoint(self) -> torch.Tensor:
+        return torch.empty((self.Q,) + self.shape, dtype=self.compute_dtype, device=self.device)
+
+    def init_equilibrium(self, rho: torch.Tensor, u: torch.Tensor, out: torch.Tensor | None = None,
+                         stream=None) -> torch.Tensor:
+        f = self.empty_state() if out is None else out
+        _check(lib.eselbm_init_equilibrium(
+            self._h, _dev(rho, torch.float64, self.cells), _dev(u, torch.float64, self.D * self.cells),
+            _dev(f, self.storage_dtype, self.Q * self.cells), _stream(stream)))
+        return f
+
+    def step(self, f_in: torch.Tensor, f_out: torch.Tensor, nsteps: int, tau: float, stream=None):
+        n = self.Q * self.cells
+        _check(lib.eselbm_step(self._h, _dev(f_in, self.storage_dtype, n), _dev(f_out, self.storage_dtype, n),
+                               int(nsteps), float(tau), _stream(stream)))
+
+    def stats(self, with_H: bool = False, stream=None) -> dict:
+        st = Stats()
+        status = lib.eselbm_alpha_stats(self._h, ctypes.byref(st), int(bool(with_H)), _stream(stream))
+        if status not in (OK, E_NONPOSITIVE):
+            _check(status)
+        d = st.as_dict()
+        d["status"] = status
+        return d
+
+    def moments(self, f: torch.Tensor, stream=None):
+        rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        u = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(lib.eselbm_moments(self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
+                                  _dev(rho), _dev(u), _stream(stream)))
+        return rho, u
+
+    # ---- adjoint ----------------------------------------------------------
+    def adjoint_step(self, f_n, lam_next, lam_n, tau: float, force_grad=None, stream=None):
+        n = self.Q * self.cells
+        _check(lib.eselbm_adjoint_step(
+            self._h, _dev(f_n, self.storage_dtype, n), _dev(lam_next, self.compute_dtype, n),
+            _dev(lam_n, self.compute_dtype, n), float(tau),
+            _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+            _stream(stream)))
+
+    def kinetic_loss(self, f, loss=None, lam=None, scale: float = 1.0, stream=None):
+        _check(lib.eselbm_kinetic_loss(
+            self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
+            _dev(loss, torch.float64, 1) if loss is not None else _vp(None),
+            _dev(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
+            float(scale), _stream(stream)))
+
+    def dissipation_loss(self, f, loss=None, lam=None, weight: float = 1.0, stream=None):
+        _check(lib.eselbm_dissipation_loss(
+            self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
+            _dev(loss, torch.float64, 1) if loss is not None else _vp(None),
+            _dev(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
+            float(weight), _stream(stream)))
+
+    def equilibrium_vjp(self, rho, u, lam, stream=None) -> torch.Tensor:
+        gu = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=self.device)
+        _check(lib.eselbm_equilibrium_vjp(
+            self._h, _dev(rho, torch.float64, self.cells), _dev(u, torch.float64, self.D * self.cells),
+            _dev(lam, self.compute_dtype, self.Q * self.cells), _dev(gu), _stream(stream)))
+        return gu
+
+
+def beta_of_tau(tau: float) -> float:
+    return 1.0 / (2.0 * tau + 1.0)
