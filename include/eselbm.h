@@ -27,6 +27,9 @@
  *   ESELBM_F32          float populations, float arithmetic.
  *   ESELBM_F16_SHIFTED  _Float16 deviations f_i - w_i (rho0 = 1), float
  *                       arithmetic.
+ *   ESELBM_F32_SHIFTED  float deviations f_i - w_i (rho0 = 1), float
+ *                       arithmetic: the same bytes as ESELBM_F32 with a
+ *                       storage rounding error about 10x smaller.
  * Accumulated diagnostics are always double.  The "compute type" below is
  * double for ESELBM_F64 and float otherwise.
  *
@@ -61,7 +64,7 @@ extern "C" {
 typedef struct eselbm_ctx *eselbm_handle;
 
 typedef enum { ESELBM_D2Q9 = 0, ESELBM_D3Q27 = 1 } eselbm_lattice;
-typedef enum { ESELBM_F64 = 0, ESELBM_F32 = 1, ESELBM_F16_SHIFTED = 2 } eselbm_dtype;
+typedef enum { ESELBM_F64 = 0, ESELBM_F32 = 1, ESELBM_F16_SHIFTED = 2, ESELBM_F32_SHIFTED = 3 } eselbm_dtype;
 /* HIGHER: alpha_Higher (Sec. IV B, App. D), the default.
  * BGK:    alpha = 2 everywhere, no gate or guard (standard LBGK, Sec. II).
  * LOWER:  alpha_Lower (Sec. IV A, Eq. alphaLowerSoln) with the same gate
@@ -183,11 +186,14 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
 /* Dissipation loss term of one state and its seed (not in the paper):
  * L = weight * sum_x |omega(x)|^2 with omega the vorticity from periodic
  * second-order central differences of u (u includes the half-force
- * shift when a force is registered).  The value is ADDED to *loss_dev.
- * weight * dL/df is ADDED to lam (compute type).  Either output may be
- * NULL. */
+ * shift F/(2 rho) when a force is registered).  The value is ADDED to
+ * *loss_dev; dL/df is ADDED to lam (compute type); with a force registered,
+ * the direct part of dL/dF (through the half-force shift of u) is ADDED to
+ * force_grad (device float [D][cells]).  Any output may be NULL.
+ * Scratch: the first call on a grid allocates two device fields of 3 floats
+ * per cell, kept for later calls (released when the process ends). */
 eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
-                                      double weight, void *stream);
+                                      double weight, void *force_grad, void *stream);
 
 /* Adjoint of eselbm_init_equilibrium with respect to u (rho held fixed):
  * grad_u[a][x] = sum_i lam[i][x] d feq_i(rho, u)/d u_a.

@@ -66,7 +66,7 @@ class Rollout:
         w = None if self.diss_weight is None else self.diss_weight * float(diss_grad)
         n_end = self.nsteps
         if w:
-            s.dissipation_loss(self._state_at_end(), lam=lam, weight=w)
+            s.dissipation_loss(self._state_at_end(), lam=lam, weight=w, force_grad=force_grad)
         seg_starts = sorted(self.ckpts)
         for start in reversed(seg_starts):
             stop = min(start + self.K, n_end)
@@ -81,7 +81,7 @@ class Rollout:
                 s.adjoint_step(f_n, lam, other, self.tau, force_grad=force_grad)
                 lam, other = other, lam
                 if w and n >= 1:
-                    s.dissipation_loss(f_n, lam=lam, weight=w)
+                    s.dissipation_loss(f_n, lam=lam, weight=w, force_grad=force_grad)
             n_end = start
         return lam
 

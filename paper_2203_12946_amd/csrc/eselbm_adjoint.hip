@@ -146,7 +146,7 @@ __global__ __launch_bounds__(256) void k_adjoint(AdjArgs a)
     } else {
         const T rho = T(1) + drho;
         const T ir = rcp_(rho);
-        T u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : T(0)};
+        T u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : T(0)};
         T feqt[Q];
         equilibrium_shifted<D, T>(drho, u, feqt);
         T xv[Q];
@@ -420,9 +420,11 @@ hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s)
     if (a.g.D == 2) {
         if (dtype == 0) return launch_adj_m<2, double>(mode, a, s);
         if (dtype == 1) return launch_adj_m<2, float>(mode, a, s);
+        if (dtype == 3) return launch_adj_m<2, f32s>(mode, a, s);
     } else {
         if (dtype == 0) return launch_adj_m<3, double>(mode, a, s);
         if (dtype == 1) return launch_adj_m<3, float>(mode, a, s);
+        if (dtype == 3) return launch_adj_m<3, f32s>(mode, a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -475,6 +477,8 @@ static hipError_t launch_kin_d(int dtype, const Grid &g, const void *f, double *
         hipLaunchKernelGGL((k_kinetic<D, double>), grid, block, 0, s, g, (const double *)f, loss, (double *)lam, scale);
     else if (dtype == 1)
         hipLaunchKernelGGL((k_kinetic<D, float>), grid, block, 0, s, g, (const float *)f, loss, (float *)lam, scale);
+    else if (dtype == 3)
+        hipLaunchKernelGGL((k_kinetic<D, f32s>), grid, block, 0, s, g, (const f32s *)f, loss, (float *)lam, scale);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -497,7 +501,7 @@ struct Scratch {
     float *vort;  // [nv][N], nv = 1 (2-D) or 3 (3-D)
 };
 
-// ring buffers of scratch, one per device, grown on demand
+// scratch fields, grown on demand (single device per process)
 static Scratch g_scratch = {nullptr, nullptr};
 static long long g_scratch_cells = 0;
 
@@ -587,7 +591,7 @@ __global__ __launch_bounds__(256) void k_vorticity(Grid g, const float *__restri
 template <int D, typename S>
 __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const S *__restrict__ f, const float *__restrict__ force,
                                                    const float *__restrict__ vort, typename Storage<S>::T *lam,
-                                                   double weight)
+                                                   double weight, float *force_grad)
 {
     using T = typename Storage<S>::T;
     constexpr int Q = Lat<D>::Q;
@@ -619,18 +623,25 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const S *__restrict__
 #pragma unroll
     for (int c = 0; c < D; ++c) u[c] = (j[c] + (force ? 0.5 * (double)force[(long long)c * g.N + cell] : 0.0)) / r;
     // du_c/df_i = (c_ic - u_c) / rho
+    if (lam) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        double s = 0.0;
+        for (int i = 0; i < Q; ++i) {
+            double s = 0.0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) s += ub[c] * (Lat<D>::c(i, c) - u[c]);
-        lam[(long long)i * g.N + cell] += (T)(s / r);
+            for (int c = 0; c < D; ++c) s += ub[c] * (Lat<D>::c(i, c) - u[c]);
+            lam[(long long)i * g.N + cell] += (T)(s / r);
+        }
+    }
+    // du_c/dF_c = 1 / (2 rho) through the half-force shift
+    if (force_grad) {
+#pragma unroll
+        for (int c = 0; c < D; ++c) force_grad[(long long)c * g.N + cell] += (float)(0.5 * ub[c] / r);
     }
 }
 
 template <int D>
 static hipError_t launch_diss_d(int dtype, const Grid &g, const void *f, const float *force, double *loss, void *lam,
-                                double weight, hipStream_t s)
+                                double weight, float *force_grad, hipStream_t s)
 {
     hipError_t e = ensure_scratch(g);
     if (e != hipSuccess) return e;
@@ -639,25 +650,30 @@ static hipError_t launch_diss_d(int dtype, const Grid &g, const void *f, const f
         hipLaunchKernelGGL((k_velocity<D, double>), grid, block, 0, s, g, (const double *)f, force, g_scratch.u);
     else if (dtype == 1)
         hipLaunchKernelGGL((k_velocity<D, float>), grid, block, 0, s, g, (const float *)f, force, g_scratch.u);
+    else if (dtype == 3)
+        hipLaunchKernelGGL((k_velocity<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, g_scratch.u);
     else
         return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_vorticity<D>), grid, block, 0, s, g, g_scratch.u, g_scratch.vort, loss, weight);
-    if (lam) {
+    if (lam || force_grad) {
         if (dtype == 0)
             hipLaunchKernelGGL((k_diss_seed<D, double>), grid, block, 0, s, g, (const double *)f, force, g_scratch.vort,
-                               (double *)lam, weight);
-        else
+                               (double *)lam, weight, force_grad);
+        else if (dtype == 1)
             hipLaunchKernelGGL((k_diss_seed<D, float>), grid, block, 0, s, g, (const float *)f, force, g_scratch.vort,
-                               (float *)lam, weight);
+                               (float *)lam, weight, force_grad);
+        else
+            hipLaunchKernelGGL((k_diss_seed<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, g_scratch.vort,
+                               (float *)lam, weight, force_grad);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_dissipation_loss(int dtype, const Grid &g, const void *f, const float *force, double *loss,
-                                   void *lam, double weight, hipStream_t s)
+                                   void *lam, double weight, float *force_grad, hipStream_t s)
 {
-    return g.D == 2 ? launch_diss_d<2>(dtype, g, f, force, loss, lam, weight, s)
-                    : launch_diss_d<3>(dtype, g, f, force, loss, lam, weight, s);
+    return g.D == 2 ? launch_diss_d<2>(dtype, g, f, force, loss, lam, weight, force_grad, s)
+                    : launch_diss_d<3>(dtype, g, f, force, loss, lam, weight, force_grad, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -692,11 +708,11 @@ hipError_t launch_equilibrium_vjp(int dtype, const Grid &g, const double *rho, c
     const dim3 grid((unsigned)((g.N + 255) / 256)), block(256);
     if (g.D == 2) {
         if (dtype == 0) hipLaunchKernelGGL((k_eq_vjp<2, double>), grid, block, 0, s, g, rho, u, (const double *)lam, grad_u);
-        else if (dtype == 1) hipLaunchKernelGGL((k_eq_vjp<2, float>), grid, block, 0, s, g, rho, u, (const float *)lam, grad_u);
+        else if (dtype == 1 || dtype == 3) hipLaunchKernelGGL((k_eq_vjp<2, float>), grid, block, 0, s, g, rho, u, (const float *)lam, grad_u);
         else return hipErrorInvalidValue;
     } else {
         if (dtype == 0) hipLaunchKernelGGL((k_eq_vjp<3, double>), grid, block, 0, s, g, rho, u, (const double *)lam, grad_u);
-        else if (dtype == 1) hipLaunchKernelGGL((k_eq_vjp<3, float>), grid, block, 0, s, g, rho, u, (const float *)lam, grad_u);
+        else if (dtype == 1 || dtype == 3) hipLaunchKernelGGL((k_eq_vjp<3, float>), grid, block, 0, s, g, rho, u, (const float *)lam, grad_u);
         else return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -40,7 +40,7 @@ static eselbm_status hip_fail(hipError_t e, const char *where)
     return ESELBM_E_HIP;
 }
 
-static size_t elem_size(int dtype) { return dtype == ESELBM_F64 ? 8 : (dtype == ESELBM_F32 ? 4 : 2); }
+static size_t elem_size(int dtype) { return dtype == ESELBM_F64 ? 8 : (dtype == ESELBM_F16_SHIFTED ? 2 : 4); }
 
 extern "C" {
 
@@ -51,7 +51,7 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
     if (!out) return fail(ESELBM_E_ARG, "eselbm_create: out is NULL");
     *out = nullptr;
     if (lattice != ESELBM_D2Q9 && lattice != ESELBM_D3Q27) return fail(ESELBM_E_ARG, "eselbm_create: unknown lattice");
-    if (dtype < ESELBM_F64 || dtype > ESELBM_F16_SHIFTED) return fail(ESELBM_E_ARG, "eselbm_create: unknown dtype");
+    if (dtype < ESELBM_F64 || dtype > ESELBM_F32_SHIFTED) return fail(ESELBM_E_ARG, "eselbm_create: unknown dtype");
     if (nx < 1 || ny < 1 || nz < 1) return fail(ESELBM_E_ARG, "eselbm_create: grid dimensions must be >= 1");
     if (lattice == ESELBM_D2Q9 && nz != 1) return fail(ESELBM_E_ARG, "eselbm_create: D2Q9 needs nz == 1");
     const int Q = lattice == ESELBM_D2Q9 ? 9 : 27;
@@ -254,11 +254,13 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
 }
 
 eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam, double weight,
-                                      void *stream)
+                                      void *force_grad, void *stream)
 {
     if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: NULL argument");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: F16 storage");
-    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, loss_dev, lam, weight, (hipStream_t)stream);
+    if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: force_grad without a registered force");
+    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, loss_dev, lam, weight, (float *)force_grad,
+                                           (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_loss: launch");
     return ESELBM_OK;
 }

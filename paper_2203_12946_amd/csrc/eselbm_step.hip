@@ -112,7 +112,7 @@ struct StepOcc {
 };
 template <>
 struct StepOcc<double> {
-    static constexpr int waves = 2;
+    static constexpr int waves = 1;
 };
 
 template <int D, typename S, int MODE, bool DIAG, bool FORCE>
@@ -142,60 +142,73 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepOcc<S>:
         const long long row0 = ((long long)z * ny + y) * nx;
         const long long cell = row0 + x;
 
-        // g: populations, gt = g - w: deviations.  Each population's source
-        // row is block-uniform; only the x offset varies per lane.
-        T g[Q], gt[Q];
+        // p: the stored values as arithmetic type -- the populations g, or
+        // their deviations g - w for shifted storage.  Only p and d = feq - g
+        // stay live as Q-arrays; g and g - w are formed on the fly (g - w is
+        // exact in floating point for g within a factor two of w).
+        // Each population's source row is block-uniform; only the x offset
+        // varies per lane.
+        constexpr bool SH = Storage<S>::kShifted;
+        T p[Q];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             const int cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1, cx = Lat<D>::c(i, 0) + 1;
             const S *rowp = fin + ((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
-            const T r = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
-            const T w = T(Lat<D>::w(i));
-            gt[i] = Storage<S>::kShifted ? r : r - w;
-            g[i] = Storage<S>::kShifted ? w + r : r;
+            p[i] = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
         }
+        auto dev = [&](int i) { return SH ? p[i] : p[i] - T(Lat<D>::w(i)); };
 
-        T drho, j[3];
-        moments_shifted<D, T>(gt, drho, j);
-        T gmin = g[0];
+        T drho = T(0), j[3] = {T(0), T(0), T(0)};
+        // positivity by comparisons (a min over raw loaded values would make
+        // the compiler keep quieted copies of all of them)
+        bool pos = true;
 #pragma unroll
-        for (int i = 1; i < Q; ++i) gmin = fmin_(gmin, g[i]);
-        // NaN in any population propagates into drho; fmin ignores it
-        const bool ok = gmin > T(0) && abs_(drho) < T(1e30);
+        for (int i = 0; i < Q; ++i) {
+            const T v = dev(i);
+            drho += v;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                if (Lat<D>::c(i, c) > 0) j[c] += v;
+                if (Lat<D>::c(i, c) < 0) j[c] -= v;
+            }
+            pos = pos && (gval<D, T, SH>(i, p) > T(0));
+        }
+        // NaN in any population fails its comparison and propagates into drho
+        const bool ok = pos && abs_(drho) < T(1e30);
         const T rho = T(1) + drho;
         T alpha = T(0);
         CellInfo info{0, 0, 0};
         T dd[Q];
-        T ab = T(0);  // the output is g + ab * dd
+        T ab = T(0);  // the output is p + ab * dd
         if (ok) {
             const T ir = rcp_(rho);
-            T u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : T(0)};
-            T feqt[Q];
-            equilibrium_shifted<D, T>(drho, u, feqt);
+            T u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : T(0)};
+            {
+                const Equilibrium<D, T> eq(drho, u);
 #pragma unroll
-            for (int i = 0; i < Q; ++i) dd[i] = feqt[i] - gt[i];
-            alpha = path_length<D, T, MODE>(g, dd, beta, info);
+                for (int i = 0; i < Q; ++i) dd[i] = eq.dev(i) - dev(i);
+            }
+            conserve_moments<D, T>(dd);
+            alpha = path_length<D, T, MODE, SH>(p, dd, beta, info);
             ab = alpha * beta;
             if (FORCE) {
                 T uf[3] = {u[0], u[1], u[2]};
 #pragma unroll
                 for (int c = 0; c < D; ++c) uf[c] += (T)a.force[(long long)c * N + cell] * ir;
-                T feqf[Q];
-                equilibrium_shifted<D, T>(drho, uf, feqf);
+                const Equilibrium<D, T> eq(drho, u), eqf(drho, uf);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) dd[i] = ab * dd[i] + (feqf[i] - feqt[i]);
+                for (int i = 0; i < Q; ++i) dd[i] = ab * dd[i] + (eqf.dev(i) - eq.dev(i));
                 ab = T(1);
             }
         } else {
 #pragma unroll
             for (int i = 0; i < Q; ++i) dd[i] = T(0);
         }
-        // post-collision population g + alpha beta (feq - g) [+ force term]
+        // post-collision value p + alpha beta (feq - g) [+ force term]
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             S *orow = fout + ((long long)i * N + row0);
-            const T v = ab * dd[i] + (Storage<S>::kShifted ? gt[i] : g[i]);
-            *lane_ptr(orow, (unsigned)x) = Storage<S>::from_T(v);
+            *lane_ptr(orow, (unsigned)x) = Storage<S>::from_T(ab * dd[i] + p[i]);
         }
 
         if (DIAG) {
@@ -266,6 +279,7 @@ static hipError_t launch_step_d(int dtype, int mode, bool diag, const StepArgs &
     case 0: return launch_step_m<D, double>(mode, diag, a, s);
     case 1: return launch_step_m<D, float>(mode, diag, a, s);
     case 2: return launch_step_m<D, _Float16>(mode, diag, a, s);
+    case 3: return launch_step_m<D, f32s>(mode, diag, a, s);
     }
     return hipErrorInvalidValue;
 }
@@ -327,6 +341,7 @@ static hipError_t launch_init_eq_d(int dtype, const Grid &g, const double *rho, 
     case 0: hipLaunchKernelGGL((k_init_eq<D, double>), grid, block, 0, s, g, rho, u, (double *)f); break;
     case 1: hipLaunchKernelGGL((k_init_eq<D, float>), grid, block, 0, s, g, rho, u, (float *)f); break;
     case 2: hipLaunchKernelGGL((k_init_eq<D, _Float16>), grid, block, 0, s, g, rho, u, (_Float16 *)f); break;
+    case 3: hipLaunchKernelGGL((k_init_eq<D, f32s>), grid, block, 0, s, g, rho, u, (f32s *)f); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -376,6 +391,7 @@ static hipError_t launch_moments_d(int dtype, const Grid &g, const void *f, cons
     case 0: hipLaunchKernelGGL((k_moments<D, double>), grid, block, 0, s, g, (const double *)f, force, rho, u); break;
     case 1: hipLaunchKernelGGL((k_moments<D, float>), grid, block, 0, s, g, (const float *)f, force, rho, u); break;
     case 2: hipLaunchKernelGGL((k_moments<D, _Float16>), grid, block, 0, s, g, (const _Float16 *)f, force, rho, u); break;
+    case 3: hipLaunchKernelGGL((k_moments<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, rho, u); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -430,6 +446,7 @@ static hipError_t launch_H_d(int dtype, const Grid &g, const void *f, DevStats *
     case 0: hipLaunchKernelGGL((k_H<D, double>), grid, block, 0, s, g, (const double *)f, st); break;
     case 1: hipLaunchKernelGGL((k_H<D, float>), grid, block, 0, s, g, (const float *)f, st); break;
     case 2: hipLaunchKernelGGL((k_H<D, _Float16>), grid, block, 0, s, g, (const _Float16 *)f, st); break;
+    case 3: hipLaunchKernelGGL((k_H<D, f32s>), grid, block, 0, s, g, (const f32s *)f, st); break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -54,7 +54,7 @@ hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s);
 hipError_t launch_kinetic_loss(int dtype, const Grid &g, const void *f, double *loss, void *lam,
                                double scale, hipStream_t s);
 hipError_t launch_dissipation_loss(int dtype, const Grid &g, const void *f, const float *force,
-                                   double *loss, void *lam, double weight, hipStream_t s);
+                                   double *loss, void *lam, double weight, float *force_grad, hipStream_t s);
 hipError_t launch_equilibrium_vjp(int dtype, const Grid &g, const double *rho, const double *u,
                                   const void *lam, double *grad_u, hipStream_t s);
 

@@ -59,6 +59,20 @@ struct Storage<float> {
     __device__ static double full(float s, double) { return (double)s; }
 };
 
+// single-precision deviations f - w (the F32-shifted storage type)
+struct f32s {
+    float v;
+};
+
+template <>
+struct Storage<f32s> {
+    using T = float;
+    static constexpr bool kShifted = true;
+    __device__ static T to_T(f32s s) { return s.v; }
+    __device__ static f32s from_T(T v) { return f32s{v}; }
+    __device__ static double full(f32s s, double w) { return w + (double)s.v; }
+};
+
 template <>
 struct Storage<_Float16> {
     using T = float;
@@ -84,11 +98,33 @@ __device__ inline S *lane_ptr(S *row, unsigned xi)
 // Fast reciprocal / square root: v_rcp_f32 and v_sqrt_f32 (about 1 ulp) in
 // single precision, correctly rounded operations in double precision.
 __device__ inline float rcp_(float v) { return __builtin_amdgcn_rcpf(v); }
-__device__ inline double rcp_(double v) { return 1.0 / v; }
+__device__ inline double rcp_(double v)
+{
+    // v_rcp_f64 refined by two Newton steps to full double precision
+    double r = __builtin_amdgcn_rcp(v);
+    r = __builtin_fma(r, __builtin_fma(-v, r, 1.0), r);
+    return __builtin_fma(r, __builtin_fma(-v, r, 1.0), r);
+}
 __device__ inline float sqrt_(float v) { return __builtin_amdgcn_sqrtf(v); }
 __device__ inline double sqrt_(double v) { return __builtin_sqrt(v); }
 __device__ inline float abs_(float v) { return __builtin_fabsf(v); }
 __device__ inline double abs_(double v) { return __builtin_fabs(v); }
+
+__device__ inline float fma_(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ inline double fma_(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// u = j / rho, correct to rounding and unbiased.  The collision conserves
+// momentum only as well as rho * u reproduces j; a quotient with a biased
+// error (the raw reciprocal's) would change the momentum by the same
+// relative amount every step and the defect would grow linearly.  One Newton
+// correction with the residual j - rho u0 formed exactly by a fused
+// multiply-add removes it.
+template <typename T>
+__device__ inline T quot_(T j, T rho, T r)
+{
+    const T u0 = j * r;
+    return fma_(r, fma_(-rho, u0, j), u0);
+}
 
 enum Mode { MODE_HIGHER = 0, MODE_BGK = 1, MODE_LOWER = 2 };
 
@@ -131,6 +167,73 @@ __device__ inline T product_deviation(int i, const T (&F)[3][3], const T (&P)[3]
     const int cz = Lat<D>::c(i, 2) + 1;
     const T wy = T(Lat<D>::w1(cy - 1));
     return P[0][cx] * (F[1][cy] * F[2][cz]) + wx * (P[1][cy] * F[2][cz] + wy * P[2][cz]);
+}
+
+// The equilibrium of one cell as a set of per-axis factors; dev(i) returns
+// feq_i - w_i without materialising all Q values (D3Q27 uses the pair
+// products A = F_y F_z and B = P_y F_z + w_y P_z, so prod - w = P_x A + w_x B).
+template <int D, typename T>
+struct Equilibrium {
+    T F[3][3], P[3][3], A[3][3], B[3][3];
+    T drho, rho;
+    __device__ Equilibrium(T drho_, const T (&u)[3]) : drho(drho_), rho(T(1) + drho_)
+    {
+        axis_factors<D, T>(u, F, P);
+        if (D == 3) {
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy)
+#pragma unroll
+                for (int cz = 0; cz < 3; ++cz) {
+                    A[cy][cz] = F[1][cy] * F[2][cz];
+                    B[cy][cz] = P[1][cy] * F[2][cz] + T(Lat<D>::w1(cy - 1)) * P[2][cz];
+                }
+        }
+    }
+    __device__ T dev(int i) const
+    {
+        const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
+        T pt;
+        if (D == 2) pt = P[0][cx] * F[1][cy] + T(Lat<D>::w1(cx - 1)) * P[1][cy];
+        else pt = P[0][cx] * A[cy][cz] + T(Lat<D>::w1(cx - 1)) * B[cy][cz];
+        return drho * T(Lat<D>::w(i)) + rho * pt;
+    }
+};
+
+// Mass and momentum exact to rounding.  The equilibrium has the moments rho
+// and j exactly in exact arithmetic, so sum_i d_i = 0 and sum_i c_i d_i = 0
+// for d = feq - g.  In floating point the per-axis factors do not sum to
+// exactly one, and the resulting moment error is a deterministic function
+// of the cell's state: it would act as a bias and accumulate step after
+// step.  Four deviations -- those of the populations (1,0,0), (0,1,0),
+// (0,0,1) and the rest population -- are therefore taken from the two
+// constraints instead of from the formula (equal in exact arithmetic).
+template <int D>
+__host__ __device__ constexpr int lat_index(int cx, int cy, int cz)
+{
+    return D == 2 ? (cx + 1) + 3 * (cy + 1) : (cx + 1) + 3 * (cy + 1) + 9 * (cz + 1);
+}
+
+template <int D, typename T>
+__device__ inline void conserve_moments(T (&d)[Lat<D>::Q])
+{
+    constexpr int Q = Lat<D>::Q;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        const int ia = lat_index<D>(a == 0, a == 1, a == 2);
+        T s = T(0);
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            if (i == ia) continue;
+            if (Lat<D>::c(i, a) > 0) s += d[i];
+            if (Lat<D>::c(i, a) < 0) s -= d[i];
+        }
+        d[ia] = -s;
+    }
+    T s0 = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i)
+        if (i != Lat<D>::REST) s0 += d[i];
+    d[Lat<D>::REST] = -s0;
 }
 
 template <int D, typename T>
@@ -229,16 +332,17 @@ constexpr double kSeriesX = 0.02;
 constexpr double kGate = 1e-3;
 
 template <typename T>
-__device__ inline T fmin_(T a, T b) { return a < b ? a : b; }
+__device__ inline T fmin_(T a, T b) { return __builtin_fmin(a, b); }
 template <>
 __device__ inline float fmin_(float a, float b) { return __builtin_fminf(a, b); }
-template <>
-__device__ inline double fmin_(double a, double b) { return __builtin_fmin(a, b); }
 template <typename T>
 __device__ inline T fmax_(T a, T b) { return __builtin_fmax(a, b); }
 template <>
 __device__ inline float fmax_(float a, float b) { return __builtin_fmaxf(a, b); }
 
+// alpha_Higher from the coefficients: b (Eq. qaud_tight_coeff), h as the
+// positive root of H_2 (Eq. gaplhah0, a2 of Eq. a2def), a with the upper
+// bound h, and the positive root of Eq. qaud_tight.
 template <typename T>
 __device__ inline T higher_from_coeffs(T aL, T b1, T Bp, T C, T N3, T N4, T N5, T N6, T beta)
 {
@@ -251,8 +355,61 @@ __device__ inline T higher_from_coeffs(T aL, T b1, T Bp, T C, T N3, T N4, T N5, 
     return conj_root(a, b, C);
 }
 
-template <int D, typename T, int MODE>
-__device__ inline T path_length(const T (&g)[Lat<D>::Q], const T (&d)[Lat<D>::Q], T beta, CellInfo &info)
+// Population i from the stored value p_i: p is g itself, or the deviation
+// g - w when SH (shifted storage).
+template <int D, typename T, bool SH>
+__device__ inline T gval(int i, const T (&p)[Lat<D>::Q])
+{
+    return SH ? T(Lat<D>::w(i)) + p[i] : p[i];
+}
+
+// Exact rational sums from g and x (one reciprocal per population for c1 and
+// c together, one for the Omega+ fractions of b).
+template <int D, typename T, int MODE, bool SH>
+__device__ inline T alpha_exact(const T (&p)[Lat<D>::Q], const T (&x)[Lat<D>::Q], T beta)
+{
+    constexpr int Q = Lat<D>::Q;
+    T S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T xi = x[i];
+        const T gi = gval<D, T, SH>(i, p);
+        const T gx2 = gi * xi * xi;
+        S2 += gx2;
+        const T xn = xi < T(0) ? xi : T(0);
+        T v = gi * xn * xn * xn;  // g x^3 on Omega-, else 0
+        M3 += v;
+        v *= xn;
+        M4 += v;
+        v *= xn;
+        M5 += v;
+        M6 += v * xn;
+        const T q1 = T(2) + xi;
+        const T p3 = T(60) + xi * (T(90) + xi * (T(36) + T(3) * xi));
+        const T r = rcp_(q1 * p3);
+        C1 += T(2) * gx2 * p3 * r;
+        C += gx2 * (T(60) + xi * (T(60) + T(11) * xi)) * q1 * r;
+    }
+    const T b1 = T(0.5) * S2;
+    const T aL = conj_root(T(0.5) * M3, b1, C1);
+    if (MODE == MODE_LOWER) return aL;
+    T Bp = T(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const T xp = x[i] > T(0) ? x[i] : T(0);
+        const T y = aL * xp;
+        const T num = T(80) + y * (T(80) + T(19) * y);
+        const T den = T(64) + y * (T(96) + y * (T(44) + T(6) * y));
+        Bp += gval<D, T, SH>(i, p) * xp * xp * xp * num * rcp_(den);  // g x^3 R(aL x) on Omega+, else 0
+    }
+    return higher_from_coeffs(aL, b1, Bp, C, M3, M4, M5, M6, beta);
+}
+
+// Path length of one cell.  d holds feq - g on entry and on return (where
+// the exact path runs it temporarily holds x = d / g, to keep two rather
+// than three Q-arrays live).
+template <int D, typename T, int MODE, bool SH>
+__device__ inline T path_length(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>::Q], T beta, CellInfo &info)
 {
     constexpr int Q = Lat<D>::Q;
     constexpr bool SERIES = sizeof(T) == 4;
@@ -263,11 +420,9 @@ __device__ inline T path_length(const T (&g)[Lat<D>::Q], const T (&d)[Lat<D>::Q]
 
     T xmin = T(0), xabs = T(0);
     T T2 = 0, T3 = 0, T4 = 0, T5 = 0, T6 = 0, N3 = 0, N4 = 0, N5 = 0, N6 = 0;
-    T xk[SERIES ? 1 : Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const T x = d[i] * rcp_(g[i]);
-        if (!SERIES) xk[i] = x;
+        const T x = d[i] * rcp_(gval<D, T, SH>(i, p));
         xmin = fmin_(xmin, x);
         xabs = fmax_(xabs, abs_(x));
         if (SERIES) {
@@ -288,6 +443,8 @@ __device__ inline T path_length(const T (&g)[Lat<D>::Q], const T (&d)[Lat<D>::Q]
             v *= xn;
             N5 += v;
             N6 += v * xn;
+        } else {
+            d[i] = x;
         }
     }
 
@@ -309,43 +466,19 @@ __device__ inline T path_length(const T (&g)[Lat<D>::Q], const T (&d)[Lat<D>::Q]
         }
     } else {
         info.exact = 1;
-        T S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0;
+        if (SERIES) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const T xi = SERIES ? d[i] * rcp_(g[i]) : xk[SERIES ? 0 : i];
-            const T dx = d[i] * xi;  // g x^2
-            S2 += dx;
-            const T xn = fmin_(xi, T(0));
-            T v = fmin_(d[i], T(0)) * xn * xn;
-            M3 += v;
-            v *= xn;
-            M4 += v;
-            v *= xn;
-            M5 += v;
-            M6 += v * xn;
-            const T q1 = T(2) + xi;
-            const T p3 = T(60) + xi * (T(90) + xi * (T(36) + T(3) * xi));
-            const T r = rcp_(q1 * p3);
-            C1 += T(2) * dx * p3 * r;
-            C += dx * (T(60) + xi * (T(60) + T(11) * xi)) * q1 * r;
+            for (int i = 0; i < Q; ++i) d[i] *= rcp_(gval<D, T, SH>(i, p));
         }
-        const T b1 = T(0.5) * S2;
-        const T aL = conj_root(T(0.5) * M3, b1, C1);
-        if (MODE == MODE_LOWER) {
-            alpha = aL;
-        } else {
-            T Bp = T(0);
+        alpha = alpha_exact<D, T, MODE, SH>(p, d, beta);
+        if (SERIES) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                const T xi = SERIES ? d[i] * rcp_(g[i]) : xk[SERIES ? 0 : i];
-                const T xp = fmax_(xi, T(0));
-                const T y = aL * xp;
-                const T num = T(80) + y * (T(80) + T(19) * y);
-                const T den = T(64) + y * (T(96) + y * (T(44) + T(6) * y));
-                Bp += d[i] * xp * xp * num * rcp_(den);  // g x^3 R for x >= 0, else 0
-            }
-            alpha = higher_from_coeffs(aL, b1, Bp, C, M3, M4, M5, M6, beta);
+            for (int i = 0; i < Q; ++i) d[i] *= gval<D, T, SH>(i, p);
         }
+    }
+    if (!SERIES) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] *= gval<D, T, SH>(i, p);
     }
     // positivity guard (App. D)
     if (xmin < T(0)) {

@@ -15,15 +15,17 @@ import torch
 _LIB_PATH = pathlib.Path(__file__).resolve().parent / "libeselbm.so"
 
 D2Q9, D3Q27 = 0, 1
-F64, F32, F16_SHIFTED = 0, 1, 2
+F64, F32, F16_SHIFTED, F32_SHIFTED = 0, 1, 2, 3
 MODE_HIGHER, MODE_BGK, MODE_LOWER = 0, 1, 2
 OK, E_ARG, E_UNSUPPORTED, E_HIP, E_NONPOSITIVE = 0, 1, 2, 3, 4
 
-DTYPES = {"f64": F64, "f32": F32, "f16s": F16_SHIFTED}
+DTYPES = {"f64": F64, "f32": F32, "f16s": F16_SHIFTED, "f32s": F32_SHIFTED}
 MODES = {"higher": MODE_HIGHER, "bgk": MODE_BGK, "lower": MODE_LOWER}
 LATTICES = {"D2Q9": D2Q9, "D3Q27": D3Q27}
-TORCH_STORAGE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float16}
-TORCH_COMPUTE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float32}
+TORCH_STORAGE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float16,
+                 F32_SHIFTED: torch.float32}
+TORCH_COMPUTE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float32,
+                 F32_SHIFTED: torch.float32}
 
 
 class EselbmError(RuntimeError):
@@ -61,7 +63,7 @@ _SIGNATURES = {
     "eselbm_moments": [_vp, _vp, _vp, _vp, _vp],
     "eselbm_adjoint_step": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_kinetic_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
-    "eselbm_dissipation_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
+    "eselbm_dissipation_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_equilibrium_vjp": [_vp, _vp, _vp, _vp, _vp, _vp],
 }
 EXPORTS = tuple(_SIGNATURES) + ("eselbm_last_error",)
@@ -113,8 +115,8 @@ def _stream(stream=None) -> _vp:
 class Solver:
     """One periodic grid: lattice, shape (ny, nx) or (nz, ny, nx), storage dtype.
 
-    State tensors are [Q, *shape] in the storage dtype (float16 holds the
-    shifted deviations f - w).  Adjoint tensors are [Q, *shape] in the
+    State tensors are [Q, *shape] in the storage dtype ("f16s" and "f32s"
+    hold the shifted deviations f - w).  Adjoint tensors are [Q, *shape] in the
     compute dtype.
     """
 
@@ -217,12 +219,14 @@ class Solver:
             _dev(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
             float(scale), _stream(stream)))
 
-    def dissipation_loss(self, f, loss=None, lam=None, weight: float = 1.0, stream=None):
+    def dissipation_loss(self, f, loss=None, lam=None, weight: float = 1.0, force_grad=None, stream=None):
         _check(lib.eselbm_dissipation_loss(
             self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
             _dev(loss, torch.float64, 1) if loss is not None else _vp(None),
             _dev(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
-            float(weight), _stream(stream)))
+            float(weight),
+            _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+            _stream(stream)))
 
     def equilibrium_vjp(self, rho, u, lam, stream=None) -> torch.Tensor:
         gu = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=self.device)

@@ -1,0 +1,252 @@
+"""GPU adjoint (hand-written VJP kernels through the C ABI) versus
+(a) the FP64 torch reference's autograd VJP of one step, element by element,
+(b) central finite differences of the FP64 C oracle along random directions
+    for whole checkpointed rollouts (relative error <= 1e-4), and
+(c) the dot-product identity <J^T lam, v> = <lam, J v> with J v by finite
+    differences of the GPU forward step in FP64.
+"""
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import torch_ref as TR
+from paper_2203_12946_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def es():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_12946_amd import eselbm
+    return eselbm
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _t(a):
+    return torch.from_numpy(np.ascontiguousarray(a))
+
+
+def _ref_vjp(f0, lam, tau, mode, force=None):
+    """(VJP w.r.t. f, VJP w.r.t. F) of one reference step."""
+    f = _t(f0).requires_grad_(True)
+    F = None if force is None else _t(force).requires_grad_(True)
+    out = TR.step(f, tau, mode=mode, force=F)
+    (out * _t(lam)).sum().backward()
+    return f.grad.numpy(), None if F is None else F.grad.numpy()
+
+
+def _state(D, shape, seed, eps):
+    """A state away from equilibrium (cells mostly beyond the gate)."""
+    if D == 2:
+        rho, u = W.shear_layer(shape[1], ny=shape[0], u0=0.06, width=0.2)
+        u = u + 0.02 * np.random.default_rng(seed + 100).standard_normal(u.shape)
+    else:
+        rho, u = W.taylor_green_3d(0, shape=shape, u0=0.06, noise=2e-2, seed=seed)
+    f0 = oracle.init_equilibrium(rho, u)
+    # a few steps build a non-equilibrium part; then perturb
+    f0 = oracle.step(f0, 2, 1e-3)
+    rng = np.random.default_rng(seed)
+    return f0 * (1 + eps * rng.standard_normal(f0.shape))
+
+
+@pytest.mark.parametrize("mode", ["higher", "lower", "bgk"])
+@pytest.mark.parametrize("D,shape", [(2, (16, 20)), (3, (6, 7, 9))])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_step_matches_reference_vjp(es, D, shape, mode, dtype):
+    lat = "D2Q9" if D == 2 else "D3Q27"
+    f0 = _state(D, shape, 3, 2e-3)
+    tau = 2e-3
+    rng = np.random.default_rng(1)
+    lam = rng.standard_normal(f0.shape)
+    ref, _ = _ref_vjp(f0, lam, tau, mode)
+    s = es.Solver(lat, shape, dtype=dtype, mode=mode)
+    fn = _t(f0).to(s.storage_dtype).cuda()
+    ln = _t(lam).to(s.compute_dtype).cuda()
+    out = s.empty_adjoint()
+    s.adjoint_step(fn, ln, out, tau)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _log(f"[vjp {lat} {mode} {dtype}] max rel err = {err:.3e}")
+    assert err < (1e-11 if dtype == "f64" else 1e-4)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_step_guard_branch(es, dtype):
+    """Cells where the positivity guard fires: derivative through x_min."""
+    feq = oracle.equilibrium(2, 1.0, [0.0, 0.0])
+    g = feq.copy()
+    g[0] += 0.2
+    g[8] += 0.2
+    g[4] -= 0.4
+    f0 = g.reshape(9, 1, 1)
+    tau = 5e-5
+    lam = np.random.default_rng(2).standard_normal(f0.shape)
+    ref, _ = _ref_vjp(f0, lam, tau, "higher")
+    s = es.Solver("D2Q9", (1, 1), dtype=dtype)
+    out = s.empty_adjoint()
+    s.adjoint_step(_t(f0).to(s.storage_dtype).cuda(), _t(lam).to(s.compute_dtype).cuda(), out, tau)
+    got = out.double().cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _log(f"[vjp guard {dtype}] max rel err = {err:.3e}")
+    assert err < (1e-11 if dtype == "f64" else 1e-4)
+
+
+def test_adjoint_step_with_force(es):
+    shape = (6, 7, 9)
+    f0 = _state(3, shape, 4, 2e-3)
+    F = W.random_force(shape, 3, amplitude=1e-3, seed=3)
+    lam = np.random.default_rng(4).standard_normal(f0.shape)
+    tau = 2e-3
+    ref_f, ref_F = _ref_vjp(f0, lam, tau, "higher", force=F)
+    s = es.Solver("D3Q27", shape, dtype="f32")
+    Fd = _t(F).float().cuda()
+    s.set_force(Fd)
+    out = s.empty_adjoint()
+    fg = torch.zeros_like(Fd)
+    s.adjoint_step(_t(f0).float().cuda(), _t(lam).float().cuda(), out, tau, force_grad=fg)
+    e1 = np.max(np.abs(out.double().cpu().numpy() - ref_f)) / np.max(np.abs(ref_f))
+    e2 = np.max(np.abs(fg.double().cpu().numpy() - ref_F)) / np.max(np.abs(ref_F))
+    _log(f"[vjp force f32] lam err {e1:.3e}  dF err {e2:.3e}")
+    assert e1 < 1e-4 and e2 < 1e-4
+
+
+def test_kinetic_and_dissipation_seeds(es):
+    shape = (6, 7, 9)
+    f0 = _state(3, shape, 5, 1e-3)
+    F = W.random_force(shape, 3, amplitude=1e-3, seed=4)
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        s = es.Solver("D3Q27", shape, dtype=dtype)
+        fd = _t(f0).to(s.storage_dtype).cuda()
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        lam = s.empty_adjoint()
+        s.kinetic_loss(fd, loss=loss, lam=lam, scale=2.0)
+        f = _t(f0).requires_grad_(True)
+        L = TR.kinetic_energy(f)
+        L.backward()
+        assert abs(loss.item() - L.item()) <= tol * abs(L.item())
+        assert np.max(np.abs(lam.double().cpu().numpy() - 2 * f.grad.numpy())) <= tol * np.max(np.abs(f.grad.numpy()))
+        if dtype == "f32":
+            s.set_force(_t(F).float().cuda())
+            Ft = _t(F)
+        else:
+            Ft = None
+        loss.zero_()
+        lam.zero_()
+        s.dissipation_loss(fd, loss=loss, lam=lam, weight=0.5)
+        f = _t(f0).requires_grad_(True)
+        L = TR.dissipation(f, 0.5, None if Ft is None else Ft.float().double())
+        L.backward()
+        _log(f"[seeds {dtype}] diss {loss.item():.6e} ref {L.item():.6e}")
+        assert abs(loss.item() - L.item()) <= 1e-5 * abs(L.item())
+        assert np.max(np.abs(lam.double().cpu().numpy() - f.grad.numpy())) <= 1e-5 * np.max(np.abs(f.grad.numpy()))
+
+
+def _ke_np(f):
+    r, v = oracle.moments(f)
+    return 0.5 * np.sum(r * (v ** 2).sum(0))
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_rollout_kinetic_gradient_vs_oracle_fd(es, dtype):
+    """The 2-D adjoint workload at reduced size: KE after n steps as a function
+    of the initial velocity, checkpointed rollout; gradient w.r.t. u0 along
+    random directions versus central differences of the oracle."""
+    from paper_2203_12946_amd import adjoint as A
+    n, ckpt, N = 40, 10, 48
+    rho, u = W.random_divfree_2d(N, k_peak=4, u_rms=0.03, seed=3)
+    tau = W.tau_from_nu(1e-3)
+    s = es.Solver("D2Q9", (N, N), dtype=dtype)
+    r = torch.from_numpy(rho).cuda()
+    u0 = torch.from_numpy(u).cuda().requires_grad_(True)
+    f0 = A.equilibrium(s, r, u0)
+    fN, _ = A.rollout(s, f0, tau, n, ckpt)
+    L = A.kinetic_energy(s, fN)
+    L.backward()
+    grad = u0.grad.cpu().numpy()
+    rng = np.random.default_rng(7)
+    worst = 0.0
+    for _ in range(4):
+        v = rng.standard_normal(u.shape)
+        eps = 1e-5
+        lp = _ke_np(oracle.step(oracle.init_equilibrium(rho, u + eps * v), n, tau))
+        lm = _ke_np(oracle.step(oracle.init_equilibrium(rho, u - eps * v), n, tau))
+        fd = (lp - lm) / (2 * eps)
+        ad = float(np.sum(grad * v))
+        worst = max(worst, abs(ad - fd) / abs(fd))
+    _log(f"[rollout KE {dtype}] worst rel err vs FD = {worst:.3e}  (L = {L.item():.6e})")
+    assert worst < 1e-4
+
+
+def test_rollout_force_gradient_vs_oracle_fd(es):
+    """The 3-D forced adjoint workload at reduced size: accumulated dissipation
+    over n steps as a function of the body force; FP32 rollout with FP64
+    reductions versus central differences of the oracle."""
+    from paper_2203_12946_amd import adjoint as A
+    shape = (8, 10, 12)
+    n, ckpt = 12, 5
+    rho, u = W.taylor_green_3d(0, shape=shape, u0=0.1 / np.sqrt(3), noise=1e-4, seed=11)
+    F0 = W.random_force(shape, 3, amplitude=1e-6, seed=12)
+    tau = W.tau_from_nu(1e-3)
+    nu0 = 1e-3
+    s = es.Solver("D3Q27", shape, dtype="f32")
+    F = torch.from_numpy(F0).float().cuda().requires_grad_(True)
+    f0 = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    _, L = A.rollout(s, f0, tau, n, ckpt, force=F, diss_weight=nu0)
+    L.backward()
+    grad = F.grad.double().cpu().numpy()
+    F32 = F0.astype(np.float32).astype(np.float64)
+
+    def loss_np(Fv):
+        total = 0.0
+        f = oracle.init_equilibrium(rho, u)
+        for _ in range(n):
+            f = oracle.step(f, 1, tau, force=Fv)
+            total += float(TR.dissipation(_t(f), nu0, _t(Fv)))
+        return total
+
+    rng = np.random.default_rng(13)
+    worst = 0.0
+    for _ in range(3):
+        v = rng.standard_normal(F0.shape) * 1e-6
+        eps = 1.0
+        fd = (loss_np(F32 + eps * v) - loss_np(F32 - eps * v)) / (2 * eps)
+        ad = float(np.sum(grad * v))
+        worst = max(worst, abs(ad - fd) / abs(fd))
+    _log(f"[rollout force f32] worst rel err vs FD = {worst:.3e}  (L = {L.item():.6e})")
+    assert worst < 1e-4
+
+
+def test_dot_product_identity(es):
+    """<J^T lam, v> = <lam, J v> for one FP64 step, J v by central differences
+    of the GPU forward step."""
+    shape = (6, 7, 9)
+    f0 = _state(3, shape, 6, 2e-3)
+    tau = 2e-3
+    s = es.Solver("D3Q27", shape, dtype="f64")
+    rng = np.random.default_rng(8)
+    lam = rng.standard_normal(f0.shape)
+    v = rng.standard_normal(f0.shape) * f0
+    out = s.empty_adjoint()
+    s.adjoint_step(_t(f0).cuda(), _t(lam).cuda(), out, tau)
+    lhs = float(np.sum(out.cpu().numpy() * v))
+
+    def fwd(x):
+        a = _t(x).cuda()
+        b = s.empty_state()
+        s.step(a, b, 1, tau)
+        return b.cpu().numpy()
+
+    eps = 1e-6
+    jv = (fwd(f0 + eps * v) - fwd(f0 - eps * v)) / (2 * eps)
+    rhs = float(np.sum(lam * jv))
+    _log(f"[dot] lhs={lhs:.12e} rhs={rhs:.12e}")
+    assert abs(lhs - rhs) <= 1e-7 * abs(rhs)

