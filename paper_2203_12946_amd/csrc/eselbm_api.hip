@@ -54,6 +54,7 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
     if (dtype < ESELBM_F64 || dtype > ESELBM_F32_SHIFTED) return fail(ESELBM_E_ARG, "eselbm_create: unknown dtype");
     if (nx < 1 || ny < 1 || nz < 1) return fail(ESELBM_E_ARG, "eselbm_create: grid dimensions must be >= 1");
     if (lattice == ESELBM_D2Q9 && nz != 1) return fail(ESELBM_E_ARG, "eselbm_create: D2Q9 needs nz == 1");
+    if (ny > 65535 || nz > 65535) return fail(ESELBM_E_UNSUPPORTED, "eselbm_create: ny and nz must be <= 65535");
     const int Q = lattice == ESELBM_D2Q9 ? 9 : 27;
     const long long N = (long long)nx * ny * nz;
     if (N > (1LL << 40)) return fail(ESELBM_E_ARG, "eselbm_create: grid too large");

