@@ -30,7 +30,7 @@ sys.path.insert(0, str(ROOT))
 HBM_PEAK_GBS = 8000.0
 METRIC = "ESELBM MLUPS & % HBM roofline (D3Q27 FP32 vs FP64); adjoint/forward time"
 KERNEL_SOURCES = ["paper_2203_12946_amd/csrc/eselbm_step.hip", "paper_2203_12946_amd/csrc/lattice.hpp"]
-TRAFFIC_FILE = ROOT / "profiles" / "traffic_d3q27_f32_256.json"
+TRAFFIC_FILE = ROOT / "profiles" / "traffic_d3q27_f32_256.md"
 
 
 def _log(msg: str):
@@ -42,6 +42,22 @@ def kernel_hash() -> str:
     for p in KERNEL_SOURCES:
         h.update((ROOT / p).read_bytes())
     return h.hexdigest()[:16]
+
+
+def traffic_bytes():
+    """Calibrated HBM bytes per launch of the headline step kernel from the
+    committed counter summary, or None once the kernel sources have changed
+    since the counters were taken."""
+    if not TRAFFIC_FILE.exists():
+        return None
+    kv = {}
+    for line in TRAFFIC_FILE.read_text().splitlines():
+        k, sep, v = line.strip().partition(": ")
+        if sep:
+            kv[k] = v.strip()
+    if kv.get("kernel_hash") != kernel_hash():
+        return None
+    return int(kv["bytes_per_launch"])
 
 
 def time_forward(es, torch, W, wl, dtype: str, mode: str, steps: int, warmup: int, rho_d, u_d):
@@ -221,11 +237,7 @@ def main():
     achieved = bytes_per_cell * cells / (main_run["kernel_ms"] * 1e-3) / 1e9
     copy_gbs, copy_ms = copy_bandwidth(torch, 27 * 4 * cells)
     _log(f"bench: plain copy of the state footprint {copy_gbs:.0f} GB/s")
-    traffic = None
-    if TRAFFIC_FILE.exists():
-        t = json.loads(TRAFFIC_FILE.read_text())
-        if t.get("kernel_hash") == kernel_hash():
-            traffic = t.get("bytes_per_launch")
+    traffic = traffic_bytes()
 
     variants = {}
     if not args.no_variants:

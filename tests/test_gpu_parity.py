@@ -64,12 +64,9 @@ def _gpu_run(es, lattice, rho, u, nsteps, tau, dtype, mode="higher", want_alpha=
     return out
 
 
-def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None, dither=None):
+def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None):
     """The oracle; with ``storage`` ("f32", "f32s", "f16s") its state is rounded
-    to that storage format after every step (FP64 arithmetic throughout).
-    ``dither`` (a seed): round to one of the two neighbouring stored values at
-    random, up with probability equal to the fractional distance (unbiased
-    stochastic rounding) -- another equally valid rounding realisation."""
+    to that storage format after every step (FP64 arithmetic throughout)."""
     f = oracle.init_equilibrium(rho, u)
     if storage is None:
         f, alpha, counts = oracle.step(f, nsteps, tau, mode=mode, want_alpha=True)
@@ -78,15 +75,11 @@ def _oracle_run(rho, u, nsteps, tau, mode="higher", storage=None, dither=None):
         _, w = oracle.lattice(D)
         w = w.reshape((-1,) + (1,) * D)
         dt = np.float16 if storage == "f16s" else np.float32
-        gen = None if dither is None else np.random.default_rng(dither)
-
-        def rnd1(v):
-            if gen is not None:
-                v = v + (gen.random(v.shape) - 0.5) * np.spacing(np.abs(v).astype(dt)).astype(np.float64)
-            return v.astype(dt).astype(np.float64)
 
         def rnd(v):
-            return rnd1(v) if storage == "f32" else w + rnd1(v - w)
+            if storage == "f32":
+                return v.astype(np.float32).astype(np.float64)
+            return w + (v - w).astype(dt).astype(np.float64)
 
         f = rnd(f)
         for k in range(nsteps):
@@ -210,15 +203,13 @@ def test_modes_d3q27(es, mode):
 
 
 def test_strongly_nonequilibrium_exact_path(es):
-    """Large departures (|x| up to ~0.1): every cell takes the exact rational
-    path in single precision.  alpha is compared after one step, where both
-    sides start from the same state up to its rounding.  Later the near-
-    inviscid rough state (beta = 0.9998) amplifies any perturbation through
-    alpha, and the 5-step error of the oracle with its state rounded to the
-    storage format spreads over an order of magnitude between equally valid
-    rounding realisations (max|drho| from 1.5e-7 to 1.9e-6 over six measured
-    ones).  The 5-step state is therefore held to 4x the largest error of four
-    realisations: round-to-nearest and three stochastic roundings."""
+    """Large departures (|x| up to ~0.1, near-inviscid beta = 0.9998): every
+    cell takes the exact rational path, whose sums the single-precision
+    formats evaluate in double.  alpha is compared after one step, where both
+    sides start from the same state up to its rounding; the state after five
+    steps is held to the storage-rounding bound (such states amplify any
+    perturbation through alpha, and an error of alpha enters the update
+    multiplied by x relative to g)."""
     shape = (10, 12, 14)
     rng = np.random.default_rng(12)
     rho = 1.0 + 0.02 * rng.standard_normal(shape)
@@ -232,13 +223,8 @@ def test_strongly_nonequilibrium_exact_path(es):
         emul1 = _oracle_run(rho, u, 1, tau, storage=dtype)
         _compare(gpu1, ref1, 0.0, 0.0, 1e-5, 1e-3, label=f"rough {dtype} 1 step", emul=emul1)
         gpu = _gpu_run(es, "D3Q27", rho, u, 5, tau, dtype)
-        emuls = [_oracle_run(rho, u, 5, tau, storage=dtype, dither=k) for k in (None, 1, 2, 3)]
-        errs = [_errors(e, ref, 1e-4) for e in emuls]
-        worst = max(range(len(errs)), key=lambda k: errs[k][0] / errs[0][0] + errs[k][1] / errs[0][1])
-        _log(f"[rough {dtype} 5 steps] realisations: "
-             + " ".join(f"({e[0]:.2e}, {e[1]:.2e})" for e in errs))
-        _compare(gpu, ref, 4 * max(e[0] for e in errs), 4 * max(e[1] for e in errs), 1e-4, 1e-3,
-                 label=f"rough {dtype} 5 steps", emul=emuls[worst])
+        emul = _oracle_run(rho, u, 5, tau, storage=dtype)
+        _compare(gpu, ref, 0.0, 0.0, 1e-4, 1e-3, label=f"rough {dtype} 5 steps", emul=emul)
     gpu64 = _gpu_run(es, "D3Q27", rho, u, 5, tau, "f64")
     _compare(gpu64, ref, 1e-12, 1e-12, 1e-10, 0.0, label="rough f64")
 
