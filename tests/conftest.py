@@ -10,4 +10,4 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an MI355X (runs through the HIP library)")
-    config.addinivalue_line("markers", "slow: long CPU oracle runs")
+    config.addinivalue_line("markers", "slow: long runs (oracle on the host, or full-length workloads on the GPU)")
