@@ -178,27 +178,35 @@ def time_adjoint_2d(es, torch, W):
                 ratio=bwd / fwd, loss=L, grad_finite=bool(torch.isfinite(g).all().item()))
 
 
-def cpu_baseline(W, wl, seconds_target: float = 20.0):
-    """The FP64 oracle on the host cores, on a z-slab of the same workload."""
+def cpu_baseline(W, wl, seconds_target: float = 15.0):
+    """The FP64 oracle on the host cores, on a z-slab of the same workload;
+    also on one core, on a thinner slab."""
     import oracle
     rho, u = W.fields_for(wl)
-    nz = 16
-    rho_s = rho[:nz].copy()
-    u_s = u[:, :nz].copy()
-    f0 = oracle.init_equilibrium(rho_s, u_s)
-    t0 = time.perf_counter()
-    oracle.step(f0, 1, wl.tau)
-    t1 = time.perf_counter()
-    per_step = t1 - t0
-    nsteps = max(1, min(20, int(seconds_target / max(per_step, 1e-3))))
-    t0 = time.perf_counter()
-    oracle.step(f0, nsteps, wl.tau)
-    t1 = time.perf_counter()
-    cells = rho_s.size
-    return dict(value=cells * nsteps / (t1 - t0) / 1e6, unit="MLUPS", cores=oracle.num_threads(),
-                kind="oracle",
-                sample=f"{wl.shape[2]}x{wl.shape[1]}x{nz} z-slab of the {wl.name} workload, "
-                       f"{nsteps} steps, FP64, {t1 - t0:.1f} s")
+
+    def timed(nz, budget):
+        f0 = oracle.init_equilibrium(rho[:nz].copy(), u[:, :nz].copy())
+        t0 = time.perf_counter()
+        oracle.step(f0, 1, wl.tau)
+        per_step = time.perf_counter() - t0
+        nsteps = max(1, min(20, int(budget / max(per_step, 1e-3))))
+        t0 = time.perf_counter()
+        oracle.step(f0, nsteps, wl.tau)
+        dt = time.perf_counter() - t0
+        return f0[0].size * nsteps / dt / 1e6, nsteps, dt
+
+    value, nsteps, dt = timed(16, seconds_target)
+    threads = oracle.num_threads()
+    oracle.set_threads(1)
+    try:
+        value1, nsteps1, dt1 = timed(2, 0.5 * seconds_target)
+    finally:
+        oracle.set_threads(0)
+    return dict(value=value, unit="MLUPS", cores=threads, kind="oracle",
+                sample=f"{wl.shape[2]}x{wl.shape[1]}x16 z-slab of the {wl.name} workload, {nsteps} steps, FP64, "
+                       f"{dt:.1f} s on {threads} threads; one core: {wl.shape[2]}x{wl.shape[1]}x2 slab, "
+                       f"{nsteps1} steps, {dt1:.1f} s",
+                value_one_core=value1)
 
 
 def main():

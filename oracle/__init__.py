@@ -76,6 +76,8 @@ def _load():
     lib.orc_moments.restype = None
     lib.orc_num_threads.argtypes = []
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_threads.argtypes = [ctypes.c_int]
+    lib.orc_set_threads.restype = None
     _lib = lib
     return lib
 
@@ -248,6 +250,11 @@ def H(f) -> float:
 def num_threads() -> int:
     """OpenMP threads the oracle's cell loops use."""
     return int(_load().orc_num_threads())
+
+
+def set_threads(n: int) -> None:
+    """Cap the oracle's OpenMP threads at n (n < 1: back to the default)."""
+    _load().orc_set_threads(int(n))
 
 
 def beta_of_tau(tau: float) -> float:

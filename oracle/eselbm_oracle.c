@@ -434,10 +434,18 @@ void orc_moments(int D, long long N, const double *f, double *rho, double *u)
     }
 }
 
-/* Threads the OpenMP loops above use (for reporting timings). */
+/* Threads the OpenMP loops above use (for reporting timings), and a cap on
+ * them (n < 1 restores the default). */
 #ifdef _OPENMP
 #include <omp.h>
+static int orc_default_threads = 0;
 int orc_num_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n)
+{
+    if (orc_default_threads == 0) orc_default_threads = omp_get_max_threads();
+    omp_set_num_threads(n >= 1 ? n : orc_default_threads);
+}
 #else
 int orc_num_threads(void) { return 1; }
+void orc_set_threads(int n) { (void)n; }
 #endif
