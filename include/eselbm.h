@@ -179,8 +179,9 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
 
 /* Kinetic-energy loss and its seed (not in the paper):
  * L = sum_x rho |u|^2 / 2 of state f.  The value is ADDED to *loss_dev (a
- * device double).  lam (compute type, Q * cells) is overwritten with
- * scale * dL/df.  Either output may be NULL. */
+ * device double), summed in a fixed order (the same bits on every run).
+ * lam (compute type, Q * cells) is overwritten with scale * dL/df.  Either
+ * output may be NULL.  Scratch: as for eselbm_dissipation_loss. */
 eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
                                   double scale, void *stream);
 
@@ -190,9 +191,13 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
  * shift F/(2 rho) when a force is registered).  The value is ADDED to
  * *loss_dev; dL/df is ADDED to lam (compute type); with a force registered,
  * the direct part of dL/dF (through the half-force shift of u) is ADDED to
- * force_grad (device float [D][cells]).  Any output may be NULL.
- * Scratch: the first call on a grid allocates two device fields of 3 floats
- * per cell, kept for later calls (released when the process ends). */
+ * force_grad (device float [D][cells]).  Any output may be NULL.  The loss
+ * is summed in a fixed order (the same bits on every run).
+ * Scratch: the first loss call on a grid allocates library-owned device
+ * fields of 7 floats per cell (u, rho, vorticity) and one double per 64-256
+ * cells (partial sums), kept for later calls on grids no larger and released
+ * when the process ends; calls on one device share them, so calls that
+ * overlap on different streams race. */
 eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
                                       double weight, void *force_grad, void *stream);
 

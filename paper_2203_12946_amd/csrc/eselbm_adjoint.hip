@@ -28,17 +28,35 @@ __device__ inline V wave_sum_a(V v)
     return v;
 }
 
-// Block sum of a double, added to *dst with one atomic per block.
-__device__ inline void block_add(double v, double *dst)
+// Loss reductions without global atomics: each block writes its partial sum
+// (wave, then block, reduction in double) to part[block], and k_sum_parts adds
+// the partials in a fixed order to *loss.  The loss is then the same bits on
+// every run, and no block waits on a contended address.
+__device__ inline void block_partial(double v, double *part, long long blk)
 {
-    __shared__ double part[4];
+    __shared__ double red[4];
     v = wave_sum_a(v);
-    if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = v;
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     if (threadIdx.x == 0) {
         double t = 0.0;
-        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += part[w];
-        atomicAdd(dst, t);
+        for (int w = 0; w < (int)(blockDim.x + 63) / 64; ++w) t += red[w];
+        part[blk] = t;
+    }
+}
+
+__global__ __launch_bounds__(1024) void k_sum_parts(const double *__restrict__ part, long long n, double *loss)
+{
+    __shared__ double red[16];
+    double t = 0.0;
+    for (long long k = threadIdx.x; k < n; k += blockDim.x) t += part[k];
+    t = wave_sum_a(t);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = t;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v = 0.0;
+        for (int w = 0; w < (int)blockDim.x / 64; ++w) v += red[w];
+        *loss += v;
     }
 }
 
@@ -84,6 +102,30 @@ __device__ inline T prod_and_grad(int i, const T (&F)[3][3], const T (&dF)[3][3]
     return F[0][cx] * yz;
 }
 
+// sum_i l_i P_i and sum_i l_i dP_i/du for P_i = prod_a F_a(c_ia): the
+// product form contracted one axis at a time, by x-rows (populations with
+// equal c_y, c_z; population i = (c_x+1) + 3(c_y+1) + 9(c_z+1)).
+template <int D, typename T>
+__device__ inline void contract_eq(const T (&l)[Lat<D>::Q], const T (&F)[3][3], const T (&dF)[3][3], T &s,
+                                   T (&sg)[3])
+{
+    s = sg[0] = sg[1] = sg[2] = T(0);
+#pragma unroll
+    for (int fz = 0; fz < (D == 3 ? 3 : 1); ++fz)
+#pragma unroll
+        for (int fy = 0; fy < 3; ++fy) {
+            const int i0 = 3 * fy + 9 * fz;
+            const T ra = fma_(l[i0], F[0][0], fma_(l[i0 + 1], F[0][1], l[i0 + 2] * F[0][2]));
+            const T rb = fma_(l[i0], dF[0][0], fma_(l[i0 + 1], dF[0][1], l[i0 + 2] * dF[0][2]));
+            const T fzv = D == 3 ? F[2][fz] : T(1);
+            const T yz = F[1][fy] * fzv;
+            s = fma_(ra, yz, s);
+            sg[0] = fma_(rb, yz, sg[0]);
+            sg[1] = fma_(ra, dF[1][fy] * fzv, sg[1]);
+            if (D == 3) sg[2] = fma_(ra, F[1][fy] * dF[2][fz], sg[2]);
+        }
+}
+
 // Reverse of the positive root s of -A s^2 + B s - C = 0 given sbar:
 // returns (Abar, Bbar, Cbar) scale factors.
 template <typename T>
@@ -95,294 +137,464 @@ __device__ inline void root_bar(T s, T A, T B, T sbar, T &Ab, T &Bb, T &Cb)
     Cb = q;
 }
 
+// Occupancy floor of the adjoint step.  The adjoint is ALU-bound (about
+// twice its memory time); the Q values of x and of lambda, the equilibrium
+// tables and the adjoints of the sums need about 190 VGPRs in single
+// precision, so two waves per SIMD run without scratch.  At three waves
+// (168 VGPRs) the spilled version measured the same time at 128^3.
+template <typename S>
+struct AdjPolicy {
+    static constexpr int waves = 2;
+};
+
+// Adjoint (vector-Jacobian product) of one step at one cell.
+//
+// Forward, as the step computes it: g (pulled), rho, u = j / rho,
+// feq = rho P(u), d = feq - g, x = d / g, alpha (gate, series or exact
+// path, guard), f* = g + alpha beta d [+ feq(rho, u + F/rho) - feq(rho, u)].
+// Reverse, with lambda the adjoint of f* at this cell:
+//   alpha_bar = beta <lambda, d>, reversed through the roots to the adjoints
+//   of the sums: on the series path the power moments T_k = <g, x^k> and
+//   N_k = <g, x^k>_-, on the exact path the rational sums;
+//   per population the explicit g-derivative of the sums at fixed x,
+//   dir_i, and their x-derivative divided by g, xd_i (for the power moments
+//   sum_k (Tb_k + [x<0] Nb_k) x^k and its derivative in x: no reciprocal);
+//   with dx_i/dfeq_i = 1/g_i and dx_i/dg_i = -(1 + x_i)/g_i,
+//     feq_bar_i = alpha beta lambda_i + xd_i,
+//     mu_i = (1 - alpha beta) lambda_i + dir_i - (1 + x_i) xd_i,
+//   then feq = rho P(u) and u = j / rho add rho_bar + c_i . j_bar to every
+//   mu_i.  The adjoint of the pull is a push: lam_n_i(x - c_i) = mu_i(x).
+// Gated cells carry no alpha derivative; a guarded cell's alpha depends on
+// x_min alone; the Omega+- membership is that of the point.
 template <int D, typename S, int MODE, bool FORCE>
-__global__ __launch_bounds__(256) void k_adjoint(AdjArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S>::waves))) void k_adjoint(AdjArgs a)
 {
     using T = typename Storage<S>::T;
     constexpr int Q = Lat<D>::Q;
+    constexpr int K = SeriesCfg<T>::K;
+    constexpr bool SH = Storage<S>::kShifted;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const long long N = a.g.N;
-    const int nxb = (nx + (int)blockDim.x - 1) / (int)blockDim.x;
-    const int xb = (int)blockIdx.x % nxb;
-    const int row = (int)blockIdx.x / nxb;
-    const int y = row % ny, z = row / ny;
-    const int x = xb * (int)blockDim.x + (int)threadIdx.x;
+    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+    const int x = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
     if (x >= nx) return;
     const S *__restrict__ fn = (const S *)a.fn;
     const T *__restrict__ lin = (const T *)a.lam_next;
     T *__restrict__ lout = (T *)a.lam_n;
     const T beta = (T)a.beta;
 
-    const int xs[3] = {x + 1 == nx ? 0 : x + 1, x, x == 0 ? nx - 1 : x - 1};
+    const unsigned xs[3] = {x + 1 == nx ? 0u : (unsigned)x + 1u, (unsigned)x,
+                            x == 0 ? (unsigned)nx - 1u : (unsigned)x - 1u};
     const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
     const int zs[3] = {z + 1 == nz ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
-    const long long cell = ((long long)z * ny + y) * nx + x;
+    const long long row0 = ((long long)z * ny + y) * nx;
 
-    T gt[Q], lam[Q];
+    // Row starts are block-uniform.  Each access takes its row offset through
+    // an empty asm, so that it is a scalar base plus the lane's 32-bit offset:
+    // otherwise the compiler folds the lane offset into 64-bit per-lane
+    // addresses and keeps all Q of them live between the reads of a row.
+    auto opaque = [](long long o) {
+        asm volatile("" : "+s"(o));
+        return o;
+    };
+    auto lam_at = [&](int i) { return *lane_ptr(lin + opaque((long long)i * N + row0), (unsigned)x); };
+    // adjoint of the pull: lam_n_i(x - c_i) = mu_i(x)
+    auto push = [&](int i, T m) {
+        const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
+        *lane_ptr(lout + opaque((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx), xs[cx]) = m;
+    };
+
+    // v: the stored values (g, or g - w when shifted), later x; l: lambda at
+    // this cell, read here for <lambda, d> in the forward pass and again (a
+    // cache hit) once the path length has been reversed, so that its Q values
+    // are not live through the reversal
+    T v[Q], l[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
-        const long long src = (long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx + xs[cx];
-        const T r = Storage<S>::to_T(fn[src]);
-        gt[i] = Storage<S>::kShifted ? r : r - T(Lat<D>::w(i));
-        lam[i] = lin[(long long)i * N + cell];
+        const S *rowp = fn + ((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
+        v[i] = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
     }
+#pragma unroll
+    for (int i = 0; i < Q; ++i) l[i] = lam_at(i);
+    auto dev = [&](int i) { return SH ? v[i] : v[i] - T(Lat<D>::w(i)); };
 
-    // ---- forward recomputation -------------------------------------------
     T drho, j[3];
-    moments_shifted<D, T>(gt, drho, j);
-    T gmin = T(Lat<D>::w(0)) + gt[0];
+    row_moments<D, T>([&](int i) { return dev(i); }, drho, j);
+    bool pos = true;
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-        const T g = T(Lat<D>::w(i)) + gt[i];
-        gmin = g < gmin ? g : gmin;
-    }
-    const bool ok = gmin > T(0) && abs_(drho) < T(1e30);
-    T mu[Q];
-    if (!ok) {
-        // uncollided cell: out = g, so mu = lam
-#pragma unroll
-        for (int i = 0; i < Q; ++i) mu[i] = lam[i];
-    } else {
-        const T rho = T(1) + drho;
-        const T ir = rcp_(rho);
-        T u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : T(0)};
-        T feqt[Q];
-        equilibrium_shifted<D, T>(drho, u, feqt);
-        T xv[Q];
-        T xmin = T(0), xabs = T(0);
-        int imin = -1;
-        T lamd = T(0);
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const T di = feqt[i] - gt[i];
-            const T g = T(Lat<D>::w(i)) + gt[i];
-            xv[i] = di * rcp_(g);
-            if (xv[i] < xmin) {
-                xmin = xv[i];
-                imin = i;
-            }
-            const T ax = abs_(xv[i]);
-            xabs = ax > xabs ? ax : xabs;
-            lamd += lam[i] * di;
+    for (int i = 0; i < Q; ++i) pos = pos && (gval<D, T, SH>(i, v) > T(0));
+    const bool ok = pos && abs_(drho) < T(1e30);
+
+    if (ok) {
+        const T rho = T(1) + drho, ir = rcp_(rho);
+        const T u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : T(0)};
+
+        // The lambda-dependent parts of the equilibrium adjoint, taken now
+        // while lambda is loaded: sum_i lambda_i P_i and sum_i lambda_i dP_i/du
+        // for feq = rho P(u), and with forcing the same for the force term
+        // feq(rho, u_f), u_f = u + F / rho (its adjoint needs lambda only).
+        T sl, slg[3];
+        {
+            T F[3][3], dF[3][3];
+            axis_factors_d<D, T>(u, F, dF);
+            contract_eq<D, T>(l, F, dF, sl, slg);
         }
-        // forward path length with the intermediates the reverse needs
+        T slf = T(0), slfg[3] = {T(0), T(0), T(0)}, Fc[3] = {T(0), T(0), T(0)};
+        if (FORCE) {
+            T uf[3] = {u[0], u[1], u[2]};
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                Fc[c] = (T)a.force[(long long)c * N + row0 + x];
+                uf[c] += Fc[c] * ir;
+            }
+            T Ff[3][3], dFf[3][3];
+            axis_factors_d<D, T>(uf, Ff, dFf);
+            contract_eq<D, T>(l, Ff, dFf, slf, slfg);
+        }
+
+        // ---- forward: x, lambda . d, x_min, max|x| and the power moments
+        T lamd = T(0), xmin = T(0), gxm = T(1), xabs = T(0);
+        int imin = -1;
+        T Tm[K + 1], Nm[K + 1];
+#pragma unroll
+        for (int k = 0; k <= K; ++k) Tm[k] = Nm[k] = T(0);
+        {
+            const Equilibrium<D, T> eq(drho, u);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const T g = gval<D, T, SH>(i, v);
+                const T d = eq.dev(i) - dev(i);
+                lamd = fma_(l[i], d, lamd);
+                T xi = d * rcp_(g);
+                // x as one value from here on (not d and 1/g kept apart)
+                asm volatile("" : "+v"(xi));
+                if (xi < xmin) {
+                    xmin = xi;
+                    gxm = g;
+                    imin = i;
+                }
+                xabs = fmax_(xabs, abs_(xi));
+                T xk[K];
+                xk[1] = xi;
+#pragma unroll
+                for (int k = 2; k < K; ++k) xk[k] = (k % 2 == 0) ? xk[k / 2] * xk[k / 2] : xk[k - 1] * xi;
+                const T dn = fmin_(d, T(0));
+#pragma unroll
+                for (int k = 2; k <= K; ++k) Tm[k] = fma_(d, xk[k - 1], Tm[k]);
+#pragma unroll
+                for (int k = 3; k <= K; ++k) Nm[k] = fma_(dn, xk[k - 1], Nm[k]);
+                v[i] = xi;
+            }
+        }
+        // the sums are completed here: the empty asm keeps the compiler from
+        // sinking their additions past the branches below, which would keep
+        // every population's terms live instead of the Q values of x only
+#pragma unroll
+        for (int k = 2; k <= K; ++k) asm volatile("" : "+v"(Tm[k]));
+#pragma unroll
+        for (int k = 3; k <= K; ++k) asm volatile("" : "+v"(Nm[k]));
+        asm volatile("" : "+v"(lamd), "+v"(xmin), "+v"(xabs), "+v"(gxm));
+
+        // ---- forward path length, and the adjoints of the sums it used ----
+        const bool gated = MODE == MODE_BGK || xabs < T(kGate);
+        const bool exact = !gated && !(xabs < T(SeriesCfg<T>::X));
         T alpha = T(2);
-        int gated = 0, guarded = 0;
-        T S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0, aL = 0, Bp = 0, BpL = 0, b = 0, h = 0, aa = 0, b1 = 0, a1 = 0;
-        if (MODE != MODE_BGK) {
-            if (xabs < T(1e-3)) {
-                gated = 1;
+        // series path: adjoints of T_k (Tb) and N_k (Nb)
+        T Tb[K + 1], Nb[K + 1];
+#pragma unroll
+        for (int k = 0; k <= K; ++k) Tb[k] = Nb[k] = T(0);
+        // exact path: adjoints of the rational sums
+        T S2b = 0, M3b = 0, M4b = 0, M5b = 0, M6b = 0, C1b = 0, Cb = 0, Bpb = 0, aLx = 0;
+        // reverse of the three roots (Omega- sums M3..M6 are N3..N6 on both paths)
+        auto reverse_roots = [&](T aL, T a1, T b1, T C1, T Bp, T dBp, T C, T N3, T N4, T N5, T N6, T abar,
+                                 T &b1b, T &C1bo, T &Cbo, T &Bpbo, T &N3b, T &N4b, T &N5b, T &N6b, T &alpha_o) {
+            T aLb;
+            if (MODE == MODE_LOWER) {
+                alpha_o = aL;
+                aLb = abar;
+                b1b = T(0);
+                Cbo = T(0);
+                Bpbo = T(0);
             } else {
+                const T b2 = beta * beta, kk = T(2.0 / 15.0) * b2;
+                const T b = b1 - kk * aL * Bp;
+                const T a2 = b2 * N3 * T(1.0 / 6.0);
+                const T h = conj_root(a2, b, C);
+                const T hb = h * beta;
+                const T aa = b2 * (N3 * T(1.0 / 6.0) + hb * (N4 * T(-1.0 / 12.0) + hb * (N5 * T(1.0 / 20.0) +
+                                                                                       hb * N6 * T(-1.0 / 5.0))));
+                alpha_o = conj_root(aa, b, C);
+                T Ab, Bb, Cb1;
+                root_bar(alpha_o, aa, b, abar, Ab, Bb, Cb1);
+                const T dadh = b2 * beta * (N4 * T(-1.0 / 12.0) + hb * (N5 * T(2.0 / 20.0) + hb * N6 * T(-3.0 / 5.0)));
+                N3b += Ab * b2 * T(1.0 / 6.0);
+                N4b -= Ab * b2 * hb * T(1.0 / 12.0);
+                N5b += Ab * b2 * hb * hb * T(1.0 / 20.0);
+                N6b -= Ab * b2 * hb * hb * hb * T(1.0 / 5.0);
+                T A2b, Bb2, Cb2;
+                root_bar(h, a2, b, Ab * dadh, A2b, Bb2, Cb2);
+                N3b += A2b * b2 * T(1.0 / 6.0);
+                const T bbar = Bb + Bb2;
+                Cbo = Cb1 + Cb2;
+                b1b = bbar;
+                Bpbo = -bbar * kk * aL;
+                aLb = -bbar * kk * (Bp + aL * dBp);
+            }
+            T A1b, B1b, C1bb;
+            root_bar(aL, a1, b1, aLb, A1b, B1b, C1bb);
+            N3b += T(0.5) * A1b;
+            b1b += B1b;
+            C1bo = C1bb;
+        };
+
+        if (!gated && !exact) {
+            constexpr double c1k[7] = {1.0, -0.5, 0.25, -0.125, 0.0625, -0.03125, 0.015625};
+            constexpr double ck[7] = {1.0, -0.5, 1.0 / 3.0, -0.25, 0.2, -1.0 / 6.0, 57.0 / 400.0};
+            constexpr double rk[6] = {1.25, -0.625, 0.375, -0.25, 45.0 / 256.0, -65.0 / 512.0};
+            const T b1 = T(0.5) * Tm[2];
+            T C1 = T(0), C = T(0);
+#pragma unroll
+            for (int k = 2; k <= K; ++k) {
+                C1 += T(c1k[k - 2]) * Tm[k];
+                C += T(ck[k - 2]) * Tm[k];
+            }
+            const T a1 = T(0.5) * Nm[3];
+            const T aL = conj_root(a1, b1, C1);
+            // Bp = sum_m r_m aL^m P_{3+m} and dBp/daL, P_k = T_k - N_k
+            T Bp = T(0), dBp = T(0);
+            if (MODE == MODE_HIGHER) {
+                Bp = T(rk[K - 3]) * (Tm[K] - Nm[K]);
+                dBp = T(K - 3) * T(rk[K - 3]) * (Tm[K] - Nm[K]);
+#pragma unroll
+                for (int k = K - 1; k >= 3; --k) {
+                    const T t = T(rk[k - 3]) * (Tm[k] - Nm[k]);
+                    Bp = Bp * aL + t;
+                    if (k > 3) dBp = dBp * aL + T(k - 3) * t;
+                }
+            }
+            T b1b = 0, C1bo = 0, Cbo = 0, Bpbo = 0, N3b = 0, N4b = 0, N5b = 0, N6b = 0;
+            reverse_roots(aL, a1, b1, C1, Bp, dBp, C, Nm[3], Nm[4], Nm[5], Nm[6], beta * lamd, b1b, C1bo, Cbo,
+                          Bpbo, N3b, N4b, N5b, N6b, alpha);
+            Tb[2] = T(0.5) * b1b;
+#pragma unroll
+            for (int k = 2; k <= K; ++k) Tb[k] += C1bo * T(c1k[k - 2]) + Cbo * T(ck[k - 2]);
+            if (MODE == MODE_HIGHER) {
+                T am = T(1);
+#pragma unroll
+                for (int k = 3; k <= K; ++k) {
+                    const T pb = Bpbo * T(rk[k - 3]) * am;  // adjoint of P_k
+                    Tb[k] += pb;
+                    Nb[k] -= pb;
+                    am *= aL;
+                }
+            }
+            Nb[3] += N3b;
+            Nb[4] += N4b;
+            Nb[5] += N5b;
+            Nb[6] += N6b;
+        } else if (exact) {
+            // the rational sums need g: g = feq / (1 + x)
+            const Equilibrium<D, T> eq(drho, u);
+            T S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const T xi = v[i];
+                const T g = (T(Lat<D>::w(i)) + eq.dev(i)) * rcp_(T(1) + xi);
+                const T gx2 = g * xi * xi;
+                S2 += gx2;
+                const T xn = fmin_(xi, T(0));
+                T t = g * xn * xn * xn;
+                M3 += t;
+                t *= xn;
+                M4 += t;
+                t *= xn;
+                M5 += t;
+                M6 += t * xn;
+                const T q1 = T(2) + xi;
+                const T p3 = T(60) + xi * (T(90) + xi * (T(36) + T(3) * xi));
+                const T r = rcp_(q1 * p3);
+                C1 += T(2) * gx2 * p3 * r;
+                C += gx2 * (T(60) + xi * (T(60) + T(11) * xi)) * q1 * r;
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            asm volatile("" : "+v"(S2), "+v"(M3), "+v"(M4), "+v"(M5), "+v"(M6), "+v"(C1), "+v"(C));
+            const T b1 = T(0.5) * S2, a1 = T(0.5) * M3;
+            const T aL = conj_root(a1, b1, C1);
+            T Bp = T(0), dBp = T(0);
+            if (MODE == MODE_HIGHER) {
 #pragma unroll
                 for (int i = 0; i < Q; ++i) {
-                    const T xi = xv[i], g = T(Lat<D>::w(i)) + gt[i];
-                    const T gx2 = g * xi * xi;
-                    S2 += gx2;
-                    const bool neg = xi < T(0);
-                    const T gx3 = gx2 * xi, gx4 = gx3 * xi, gx5 = gx4 * xi, gx6 = gx5 * xi;
-                    M3 += neg ? gx3 : T(0);
-                    M4 += neg ? gx4 : T(0);
-                    M5 += neg ? gx5 : T(0);
-                    M6 += neg ? gx6 : T(0);
-                    const T q1 = T(2) + xi;
-                    const T p3 = T(60) + xi * (T(90) + xi * (T(36) + T(3) * xi));
-                    const T r = rcp_(q1 * p3);
-                    C1 += T(2) * gx2 * p3 * r;
-                    C += gx2 * (T(60) + xi * (T(60) + T(11) * xi)) * q1 * r;
+                    const T xi = v[i];
+                    const T xp = fmax_(xi, T(0));
+                    const T g = (T(Lat<D>::w(i)) + eq.dev(i)) * rcp_(T(1) + xi);
+                    const T yv = aL * xp;
+                    const T num = T(80) + yv * (T(80) + T(19) * yv);
+                    const T den = T(64) + yv * (T(96) + yv * (T(44) + T(6) * yv));
+                    const T rden = rcp_(den);
+                    const T R = num * rden;
+                    const T dR = ((T(80) + T(38) * yv) * den - num * (T(96) + yv * (T(88) + T(18) * yv))) * rden * rden;
+                    const T gx3 = g * xp * xp * xp;
+                    Bp += gx3 * R;
+                    dBp += gx3 * xp * dR;
+                    __builtin_amdgcn_sched_barrier(0);
                 }
-                a1 = T(0.5) * M3;
-                b1 = T(0.5) * S2;
-                aL = conj_root(a1, b1, C1);
-                if (MODE == MODE_LOWER) {
-                    alpha = aL;
-                } else {
-#pragma unroll
-                    for (int i = 0; i < Q; ++i) {
-                        const T xi = xv[i], g = T(Lat<D>::w(i)) + gt[i];
-                        const T yv = aL * xi;
-                        const T num = T(80) + yv * (T(80) + T(19) * yv);
-                        const T den = T(64) + yv * (T(96) + yv * (T(44) + T(6) * yv));
-                        const T rden = rcp_(den);
-                        const T R = num * rden;
-                        const T dR = ((T(80) + T(38) * yv) * den - num * (T(96) + yv * (T(88) + T(18) * yv))) * rden * rden;
-                        const T gx3 = g * xi * xi * xi;
-                        const bool pos = xi >= T(0);
-                        Bp += pos ? gx3 * R : T(0);
-                        BpL += pos ? gx3 * xi * dR : T(0);
-                    }
-                    const T b2 = beta * beta;
-                    b = b1 - (T(2.0 / 15.0) * aL * b2) * Bp;
-                    const T a2 = b2 * M3 * T(1.0 / 6.0);
-                    h = conj_root(a2, b, C);
-                    const T hb = h * beta;
-                    aa = b2 * (M3 * T(1.0 / 6.0) - hb * M4 * T(1.0 / 12.0) + hb * hb * M5 * T(1.0 / 20.0) -
-                               hb * hb * hb * M6 * T(1.0 / 5.0));
-                    alpha = conj_root(aa, b, C);
-                }
+                asm volatile("" : "+v"(Bp), "+v"(dBp));
             }
-            if (xmin < T(0)) {
-                const T amax = T(-1) * rcp_(beta * xmin);
-                if (alpha > amax) {
-                    alpha = T(0.5) * (T(1) + amax);
-                    guarded = 1;
-                }
+            T b1b = 0;
+            reverse_roots(aL, a1, b1, C1, Bp, dBp, C, M3, M4, M5, M6, beta * lamd, b1b, C1b, Cb, Bpb, M3b, M4b,
+                          M5b, M6b, alpha);
+            S2b = T(0.5) * b1b;
+            aLx = aL;
+        }
+        // positivity guard: alpha then depends on x_min alone
+        T xminb = T(0);
+        bool guarded = false;
+        if (!gated && xmin < T(0)) {
+            const T amax = T(-1) * rcp_(beta * xmin);
+            if (alpha > amax) {
+                alpha = T(0.5) * (T(1) + amax);
+                guarded = true;
+                xminb = beta * lamd * T(0.5) * rcp_(beta * xmin * xmin);
             }
         }
+        const bool smooth = !gated && !guarded;
         const T ab = alpha * beta;
-
-        // ---- reverse through alpha -----------------------------------------
-        const T abar = beta * lamd;
-        T S2b = 0, M3b = 0, M4b = 0, M5b = 0, M6b = 0, C1b = 0, Cb = 0, Bpb = 0;
-        T xminb = 0;  // adjoint of x_min (guard branch)
-        if (MODE != MODE_BGK && !gated) {
-            if (guarded) {
-                xminb = abar * T(0.5) * rcp_(beta * xmin * xmin);
-            } else {
-                T aLb;
-                if (MODE == MODE_LOWER) {
-                    aLb = abar;
-                } else {
-                    T Ab, Bb, Cbb;
-                    root_bar(alpha, aa, b, abar, Ab, Bb, Cbb);
-                    const T b2 = beta * beta, hb = h * beta;
-                    // a = b2 (M3/6 - hb M4/12 + hb^2 M5/20 - hb^3 M6/5)
-                    const T dadh = b2 * beta * (-M4 * T(1.0 / 12.0) + T(2) * hb * M5 * T(1.0 / 20.0) -
-                                                T(3) * hb * hb * M6 * T(1.0 / 5.0));
-                    M3b += Ab * b2 * T(1.0 / 6.0);
-                    M4b += -Ab * b2 * hb * T(1.0 / 12.0);
-                    M5b += Ab * b2 * hb * hb * T(1.0 / 20.0);
-                    M6b += -Ab * b2 * hb * hb * hb * T(1.0 / 5.0);
-                    const T hbar = Ab * dadh;
-                    T A2b, Bb2, Cb2;
-                    const T a2 = b2 * M3 * T(1.0 / 6.0);
-                    root_bar(h, a2, b, hbar, A2b, Bb2, Cb2);
-                    M3b += A2b * b2 * T(1.0 / 6.0);
-                    const T bbar = Bb + Bb2;
-                    Cb = Cbb + Cb2;
-                    // b = b1 - k aL Bp, k = 2 beta^2 / 15; Bp depends on aL
-                    const T k = T(2.0 / 15.0) * b2;
-                    S2b += T(0.5) * bbar;
-                    Bpb = -bbar * k * aL;
-                    aLb = -bbar * k * (Bp + aL * BpL);
-                }
-                T A1b, B1b, C1bb;
-                root_bar(aL, a1, b1, aLb, A1b, B1b, C1bb);
-                M3b += T(0.5) * A1b;
-                S2b += T(0.5) * B1b;
-                C1b = C1bb;
+        const T lfac = FORCE ? ab - T(1) : ab;
+        // feq enters out with weight alpha beta (alpha beta - 1 with forcing,
+        // whose term subtracts feq(rho, u)); the force term feq(rho, u_f)
+        // with weight 1
+        T rhob = fma_(lfac, sl, slf), ub[3];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) ub[c] = lfac * slg[c];
+        T ubf[3] = {T(0), T(0), T(0)};
+        if (FORCE) {
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const T fb = rho * slfg[c];
+                ubf[c] = fb;
+                rhob -= fb * Fc[c] * ir * ir;
+                if (a.force_grad) a.force_grad[(long long)c * N + row0 + x] += (float)(fb * ir);
             }
         }
 
-        // ---- per-population partials, equilibrium reverse ----------------
+        // Per population, (dir, xd): the explicit g-derivative of the
+        // path-length sums at fixed x, and their x-derivative over g (the
+        // guard's x_min population alone where the guard fired).  Two passes
+        // over the populations with the same (dir, xd): the first gathers the
+        // adjoints of rho and u through feq = rho P(u), the second forms mu_i
+        // and pushes it out, so that no Q-array of mu is live.
         T F[3][3], dF[3][3];
         axis_factors_d<D, T>(u, F, dF);
-        T rhob = T(0), ub[3] = {T(0), T(0), T(0)};
-        const bool smooth = MODE != MODE_BGK && !gated && !guarded;
+        const T xdmin = guarded ? xminb * rcp_(gxm) : T(0);
+        // x enters each pass as a fresh copy (empty asm), so that the powers
+        // of x formed in one pass are not kept live for the next
+        auto xcopy = [&](int i) {
+            T xi = v[i];
+            asm volatile("" : "+v"(xi));
+            return xi;
+        };
+        auto passes = [&](auto &&dirxd) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const T xi = xv[i], g = T(Lat<D>::w(i)) + gt[i];
-            T dir = T(0), xbar = T(0);
-            if (smooth) {
-                const T x2 = xi * xi, x3 = x2 * xi;
+            for (int i = 0; i < Q; ++i) {
+                T dir, xd;
+                dirxd(xcopy(i), dir, xd);
+                if (guarded && i == imin) xd = xdmin;
+                T gp[3];
+                const T Pi = prod_and_grad<D, T>(i, F, dF, gp);
+                rhob = fma_(xd, Pi, rhob);
+#pragma unroll
+                for (int c = 0; c < D; ++c) ub[c] = fma_(xd, gp[c], ub[c]);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+            // feq = rho P(u): dfeq/du = rho dP/du; the force term's u_f; then
+            // u = j / rho
+            T jb[3] = {T(0), T(0), T(0)};
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const T uc = ub[c] * rho + ubf[c];
+                jb[c] = uc * ir;
+                rhob -= uc * u[c] * ir;
+            }
+            // the second read of lambda (the empty asm with a memory clobber
+            // keeps the compiler from reusing the first)
+            asm volatile("" ::: "memory");
+#pragma unroll
+            for (int i = 0; i < Q; ++i) l[i] = lam_at(i);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                T dir, xd;
+                const T xi = xcopy(i);
+                dirxd(xi, dir, xd);
+                if (guarded && i == imin) xd = xdmin;
+                T m = fma_(l[i], T(1) - ab, dir) - (T(1) + xi) * xd + rhob;
+#pragma unroll
+                for (int c = 0; c < D; ++c) {
+                    if (Lat<D>::c(i, c) > 0) m += jb[c];
+                    if (Lat<D>::c(i, c) < 0) m -= jb[c];
+                }
+                push(i, m);
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        };
+        if (!(smooth && exact)) {
+            // power-series form; all coefficients are zero in gated and
+            // guarded cells.  sum_k c_k x^k and sum_k k c_k x^(k-1), with
+            // c = cN on Omega-, cP else
+            T cP[K + 1], cN[K + 1];
+#pragma unroll
+            for (int k = 2; k <= K; ++k) {
+                cP[k] = smooth ? Tb[k] : T(0);
+                cN[k] = smooth ? Tb[k] + Nb[k] : T(0);
+            }
+            passes([&](T xi, T &dir, T &xd) {
                 const bool neg = xi < T(0);
-                // S2 = <g, x^2>
-                dir += S2b * x2;
-                xbar += S2b * T(2) * xi;
-                // Omega- power moments
+                T pv = neg ? cN[K] : cP[K], pd = T(K) * pv;
+#pragma unroll
+                for (int k = K - 1; k >= 2; --k) {
+                    const T ck = neg ? cN[k] : cP[k];
+                    pv = fma_(pv, xi, ck);
+                    pd = fma_(pd, xi, T(k) * ck);
+                }
+                dir = pv * xi * xi;
+                xd = pd * xi;
+            });
+        } else {
+            // exact rationals
+            passes([&](T xi, T &dir, T &xd) {
+                const bool neg = xi < T(0);
+                const T x2 = xi * xi, x3 = x2 * xi;
+                dir = S2b * x2;
+                xd = S2b * T(2) * xi;
                 if (neg) {
                     dir += x3 * (M3b + xi * (M4b + xi * (M5b + xi * M6b)));
-                    xbar += x2 * (T(3) * M3b + xi * (T(4) * M4b + xi * (T(5) * M5b + xi * T(6) * M6b)));
+                    xd += x2 * (T(3) * M3b + xi * (T(4) * M4b + xi * (T(5) * M5b + xi * T(6) * M6b)));
                 }
-                // c1 = <g, 2x^2/(2+x)>, c = <g, x^2 N3/P3>
-                const T q1 = T(2) + xi;
-                const T iq = rcp_(q1);
-                const T phi1 = T(2) * x2 * iq;
-                const T dphi1 = T(2) * xi * (T(4) + xi) * iq * iq;
+                const T iq = rcp_(T(2) + xi);
                 const T n3 = T(60) + xi * (T(60) + T(11) * xi);
                 const T p3 = T(60) + xi * (T(90) + xi * (T(36) + T(3) * xi));
                 const T ip = rcp_(p3);
-                const T phi = x2 * n3 * ip;
                 const T dn3 = T(60) + T(22) * xi;
                 const T dp3 = T(90) + xi * (T(72) + T(9) * xi);
-                const T dphi = ((T(2) * xi * n3 + x2 * dn3) * p3 - x2 * n3 * dp3) * ip * ip;
-                dir += C1b * phi1 + Cb * phi;
-                xbar += C1b * dphi1 + Cb * dphi;
+                dir += C1b * T(2) * x2 * iq + Cb * x2 * n3 * ip;
+                xd += C1b * T(2) * xi * (T(4) + xi) * iq * iq +
+                      Cb * ((T(2) * xi * n3 + x2 * dn3) * p3 - x2 * n3 * dp3) * ip * ip;
                 if (MODE == MODE_HIGHER && !neg) {
-                    const T yv = aL * xi;
+                    const T yv = aLx * xi;
                     const T num = T(80) + yv * (T(80) + T(19) * yv);
                     const T den = T(64) + yv * (T(96) + yv * (T(44) + T(6) * yv));
                     const T rden = rcp_(den);
                     const T R = num * rden;
                     const T dR = ((T(80) + T(38) * yv) * den - num * (T(96) + yv * (T(88) + T(18) * yv))) * rden * rden;
                     dir += Bpb * x3 * R;
-                    xbar += Bpb * (T(3) * x2 * R + x3 * aL * dR);
+                    xd += Bpb * (T(3) * x2 * R + x3 * aLx * dR);
                 }
-                xbar *= g;
-            } else if (i == imin) {
-                xbar = xminb;
-            }
-            // x = feq/g - 1
-            const T ig = rcp_(g);
-            const T feqb = (FORCE ? ab - T(1) : ab) * lam[i] + xbar * ig;
-            mu[i] = lam[i] * (T(1) - ab) + dir - xbar * (T(1) + xi) * ig;
-            // feq_i = rho P_i(u)
-            T gp[3];
-            const T Pi = prod_and_grad<D, T>(i, F, dF, gp);
-            rhob += feqb * Pi;
-#pragma unroll
-            for (int c = 0; c < D; ++c) ub[c] += rho * feqb * gp[c];
+            });
         }
-        if (FORCE) {
-            T uf[3] = {u[0], u[1], u[2]};
-            T Fc[3] = {T(0), T(0), T(0)};
+    } else {
+        // uncollided cell: out = g, so mu = lambda
 #pragma unroll
-            for (int c = 0; c < D; ++c) {
-                Fc[c] = (T)a.force[(long long)c * N + cell];
-                uf[c] += Fc[c] * ir;
-            }
-            T Ff[3][3], dFf[3][3];
-            axis_factors_d<D, T>(uf, Ff, dFf);
-            T ufb[3] = {T(0), T(0), T(0)};
-#pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                T gp[3];
-                const T Pi = prod_and_grad<D, T>(i, Ff, dFf, gp);
-                rhob += lam[i] * Pi;
-#pragma unroll
-                for (int c = 0; c < D; ++c) ufb[c] += rho * lam[i] * gp[c];
-            }
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                ub[c] += ufb[c];
-                rhob -= ufb[c] * Fc[c] * ir * ir;
-                if (a.force_grad) a.force_grad[(long long)c * N + cell] += (float)(ufb[c] * ir);
-            }
-        }
-        // u = j / rho
-        T jb[3] = {T(0), T(0), T(0)};
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            jb[c] = ub[c] * ir;
-            rhob -= ub[c] * u[c] * ir;
-        }
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            T m = mu[i] + rhob;
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                if (Lat<D>::c(i, c) > 0) m += jb[c];
-                if (Lat<D>::c(i, c) < 0) m -= jb[c];
-            }
-            mu[i] = m;
-        }
-    }
-    // adjoint of the pull: lam^n_i(x - c_i) = mu_i(x)
-#pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
-        const long long dst = (long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx + xs[cx];
-        lout[dst] = mu[i];
+        for (int i = 0; i < Q; ++i) push(i, lam_at(i));
     }
 }
 
@@ -390,9 +602,8 @@ template <int D, typename S, int MODE>
 static hipError_t launch_adj_t(const AdjArgs &a, hipStream_t s)
 {
     const int bx = block_x(a.g.nx);
-    const long long nblk = (long long)((a.g.nx + bx - 1) / bx) * a.g.ny * a.g.nz;
-    if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)nblk), block(bx);
+    if (a.g.ny > 65535 || a.g.nz > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)((a.g.nx + bx - 1) / bx), (unsigned)a.g.ny, (unsigned)a.g.nz), block(bx);
     if (a.force) {
         if constexpr (std::is_same<S, float>::value) {
             hipLaunchKernelGGL((k_adjoint<D, S, MODE, true>), grid, block, 0, s, a);
@@ -434,7 +645,7 @@ hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s)
 // dL/df_i = c_i . u - |u|^2 / 2.
 // ---------------------------------------------------------------------------
 template <int D, typename S>
-__global__ __launch_bounds__(256) void k_kinetic(Grid g, const S *__restrict__ f, double *loss,
+__global__ __launch_bounds__(256) void k_kinetic(Grid g, const S *__restrict__ f, double *part,
                                                  typename Storage<S>::T *lam, double scale)
 {
     using T = typename Storage<S>::T;
@@ -451,8 +662,8 @@ __global__ __launch_bounds__(256) void k_kinetic(Grid g, const S *__restrict__ f
 #pragma unroll
             for (int c = 0; c < D; ++c) j[c] += Lat<D>::c(i, c) * v;
         }
-        const double r = 1.0 + dr;
-        double u[3] = {j[0] / r, j[1] / r, D == 3 ? j[2] / r : 0.0};
+        const double r = 1.0 + dr, ir = 1.0 / r;
+        double u[3] = {j[0] * ir, j[1] * ir, D == 3 ? j[2] * ir : 0.0};
         const double uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
         e = 0.5 * r * uu;
         if (lam) {
@@ -465,22 +676,68 @@ __global__ __launch_bounds__(256) void k_kinetic(Grid g, const S *__restrict__ f
             }
         }
     }
-    if (loss) block_add(e, loss);
+    if (part) block_partial(e, part, blockIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the losses, grown on demand (single device per process):
+// velocity and density of the state, vorticity, and one partial sum per block.
+// ---------------------------------------------------------------------------
+struct Scratch {
+    float *u = nullptr;      // [D][N], u = (j + F/2) / rho
+    float *rho = nullptr;    // [N]
+    float *vort = nullptr;   // [nv][N], nv = 1 (2-D) or 3 (3-D)
+    double *part = nullptr;  // one partial sum per block
+    long long cells = 0, parts = 0;
+};
+static Scratch g_scratch;
+
+// Blocks of the (x-block, y, z) launch used by the stencil passes; it is at
+// least the ceil(N / 256) blocks of the cell-local passes.
+static long long stencil_blocks(const Grid &g)
+{
+    const int bx = block_x(g.nx);
+    return (long long)((g.nx + bx - 1) / bx) * g.ny * g.nz;
+}
+
+static hipError_t ensure_scratch(const Grid &g)
+{
+    const long long parts = stencil_blocks(g);
+    if (g_scratch.cells >= g.N && g_scratch.parts >= parts) return hipSuccess;
+    hipFree(g_scratch.u);
+    hipFree(g_scratch.rho);
+    hipFree(g_scratch.vort);
+    hipFree(g_scratch.part);
+    g_scratch = Scratch{};
+    hipError_t e = hipMalloc((void **)&g_scratch.u, sizeof(float) * 3 * g.N);
+    if (e == hipSuccess) e = hipMalloc((void **)&g_scratch.rho, sizeof(float) * g.N);
+    if (e == hipSuccess) e = hipMalloc((void **)&g_scratch.vort, sizeof(float) * 3 * g.N);
+    if (e == hipSuccess) e = hipMalloc((void **)&g_scratch.part, sizeof(double) * parts);
+    if (e != hipSuccess) return e;
+    g_scratch.cells = g.N;
+    g_scratch.parts = parts;
+    return hipSuccess;
 }
 
 template <int D>
 static hipError_t launch_kin_d(int dtype, const Grid &g, const void *f, double *loss, void *lam, double scale,
                                hipStream_t s)
 {
-    const dim3 grid((unsigned)((g.N + 255) / 256)), block(256);
+    hipError_t e = ensure_scratch(g);
+    if (e != hipSuccess) return e;
+    const long long nblk = (g.N + 255) / 256;
+    if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nblk), block(256);
+    double *part = loss ? g_scratch.part : nullptr;
     if (dtype == 0)
-        hipLaunchKernelGGL((k_kinetic<D, double>), grid, block, 0, s, g, (const double *)f, loss, (double *)lam, scale);
+        hipLaunchKernelGGL((k_kinetic<D, double>), grid, block, 0, s, g, (const double *)f, part, (double *)lam, scale);
     else if (dtype == 1)
-        hipLaunchKernelGGL((k_kinetic<D, float>), grid, block, 0, s, g, (const float *)f, loss, (float *)lam, scale);
+        hipLaunchKernelGGL((k_kinetic<D, float>), grid, block, 0, s, g, (const float *)f, part, (float *)lam, scale);
     else if (dtype == 3)
-        hipLaunchKernelGGL((k_kinetic<D, f32s>), grid, block, 0, s, g, (const f32s *)f, loss, (float *)lam, scale);
+        hipLaunchKernelGGL((k_kinetic<D, f32s>), grid, block, 0, s, g, (const f32s *)f, part, (float *)lam, scale);
     else
         return hipErrorInvalidValue;
+    if (loss) hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (const double *)part, nblk, loss);
     return hipGetLastError();
 }
 
@@ -493,38 +750,13 @@ hipError_t launch_kinetic_loss(int dtype, const Grid &g, const void *f, double *
 
 // ---------------------------------------------------------------------------
 // Dissipation loss L = weight * sum |omega|^2, omega from periodic central
-// differences of u = (j + F/2) / rho.  Three passes over small scratch
-// fields: velocity, vorticity (+ loss), then the seed.
+// differences of u = (j + F/2) / rho.  Three passes: velocity and density
+// (reads the state once), vorticity (+ loss), then the seed from u, rho and
+// the vorticity.
 // ---------------------------------------------------------------------------
-struct Scratch {
-    float *u;     // [D][N]
-    float *vort;  // [nv][N], nv = 1 (2-D) or 3 (3-D)
-};
-
-// scratch fields, grown on demand (single device per process)
-static Scratch g_scratch = {nullptr, nullptr};
-static long long g_scratch_cells = 0;
-
-static hipError_t ensure_scratch(const Grid &g)
-{
-    if (g_scratch_cells >= g.N) return hipSuccess;
-    if (g_scratch.u) {
-        hipFree(g_scratch.u);
-        hipFree(g_scratch.vort);
-        g_scratch = {nullptr, nullptr};
-        g_scratch_cells = 0;
-    }
-    hipError_t e = hipMalloc((void **)&g_scratch.u, sizeof(float) * 3 * g.N);
-    if (e != hipSuccess) return e;
-    e = hipMalloc((void **)&g_scratch.vort, sizeof(float) * 3 * g.N);
-    if (e != hipSuccess) return e;
-    g_scratch_cells = g.N;
-    return hipSuccess;
-}
-
 template <int D, typename S>
 __global__ __launch_bounds__(256) void k_velocity(Grid g, const S *__restrict__ f, const float *__restrict__ force,
-                                                  float *__restrict__ uo)
+                                                  float *__restrict__ uo, float *__restrict__ ro)
 {
     constexpr int Q = Lat<D>::Q;
     const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -538,22 +770,45 @@ __global__ __launch_bounds__(256) void k_velocity(Grid g, const S *__restrict__ 
 #pragma unroll
         for (int c = 0; c < D; ++c) j[c] += Lat<D>::c(i, c) * v;
     }
-    const double r = 1.0 + dr;
+    const double r = 1.0 + dr, ir = 1.0 / r;
+    ro[cell] = (float)r;
 #pragma unroll
     for (int c = 0; c < D; ++c) {
         double jc = j[c];
         if (force) jc += 0.5 * (double)force[(long long)c * g.N + cell];
-        uo[(long long)c * g.N + cell] = (float)(jc / r);
+        uo[(long long)c * g.N + cell] = (float)(jc * ir);
     }
 }
 
-__device__ inline long long nb(const Grid &g, long long x, long long y, long long z, int axis, int dir)
-{
-    if (axis == 0) x = (x + dir + g.nx) % g.nx;
-    if (axis == 1) y = (y + dir + g.ny) % g.ny;
-    if (axis == 2) z = (z + dir + g.nz) % g.nz;
-    return (z * g.ny + y) * g.nx + x;
-}
+// Row offsets of a cell's six face neighbours on the periodic grid, for the
+// (x-block, y, z) launch: x -+ 1 as lane indices, y -+ 1 and z -+ 1 as row
+// starts (element offsets within one field).
+struct Nbr {
+    int x, xp, xm;
+    long long row, ryp, rym, rzp, rzm;
+    __device__ Nbr(const Grid &g)
+    {
+        const int nx = g.nx, ny = g.ny, nz = g.nz;
+        const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+        x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+        xp = x + 1 == nx ? 0 : x + 1;
+        xm = x == 0 ? nx - 1 : x - 1;
+        const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
+        const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
+        row = ((long long)z * ny + y) * nx;
+        ryp = ((long long)z * ny + yp) * nx;
+        rym = ((long long)z * ny + ym) * nx;
+        rzp = ((long long)zp * ny + y) * nx;
+        rzm = ((long long)zm * ny + y) * nx;
+    }
+    // value of field v at the neighbour along axis a, direction dir (+-1)
+    __device__ double at(const float *v, int a, int dir) const
+    {
+        if (a == 0) return (double)v[row + (dir > 0 ? xp : xm)];
+        if (a == 1) return (double)v[(dir > 0 ? ryp : rym) + x];
+        return (double)v[(dir > 0 ? rzp : rzm) + x];
+    }
+};
 
 // vorticity component k = (a, b): omega_k = d_a u_b - d_b u_a
 __device__ inline void vort_axes(int D, int k, int &a, int &b)
@@ -566,38 +821,37 @@ __device__ inline void vort_axes(int D, int k, int &a, int &b)
 
 template <int D>
 __global__ __launch_bounds__(256) void k_vorticity(Grid g, const float *__restrict__ u, float *__restrict__ vort,
-                                                   double *loss, double weight)
+                                                   double *part, double weight)
 {
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    const Nbr n(g);
+    const long long N = g.N;
     double e = 0.0;
-    if (cell < g.N) {
-        const long long x = cell % g.nx, y = (cell / g.nx) % g.ny, z = cell / ((long long)g.nx * g.ny);
+    if (n.x < g.nx) {
         constexpr int nv = D == 2 ? 1 : 3;
 #pragma unroll
         for (int k = 0; k < nv; ++k) {
             int a, b;
             vort_axes(D, k, a, b);
-            const double dub = 0.5 * ((double)u[b * g.N + nb(g, x, y, z, a, 1)] - (double)u[b * g.N + nb(g, x, y, z, a, -1)]);
-            const double dua = 0.5 * ((double)u[a * g.N + nb(g, x, y, z, b, 1)] - (double)u[a * g.N + nb(g, x, y, z, b, -1)]);
+            const double dub = 0.5 * (n.at(u + b * N, a, 1) - n.at(u + b * N, a, -1));
+            const double dua = 0.5 * (n.at(u + a * N, b, 1) - n.at(u + a * N, b, -1));
             const double om = dub - dua;
-            vort[k * g.N + cell] = (float)om;
+            vort[k * N + n.row + n.x] = (float)om;
             e += om * om;
         }
         e *= weight;
     }
-    if (loss) block_add(e, loss);
+    if (part) block_partial(e, part, ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
-template <int D, typename S>
-__global__ __launch_bounds__(256) void k_diss_seed(Grid g, const S *__restrict__ f, const float *__restrict__ force,
-                                                   const float *__restrict__ vort, typename Storage<S>::T *lam,
-                                                   double weight, float *force_grad)
+template <int D, typename T>
+__global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restrict__ u, const float *__restrict__ rho,
+                                                   const float *__restrict__ vort, T *lam, double weight,
+                                                   float *force_grad)
 {
-    using T = typename Storage<S>::T;
     constexpr int Q = Lat<D>::Q;
-    const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (cell >= g.N) return;
-    const long long x = cell % g.nx, y = (cell / g.nx) % g.ny, z = cell / ((long long)g.nx * g.ny);
+    const Nbr n(g);
+    if (n.x >= g.nx) return;
+    const long long N = g.N, cell = n.row + n.x;
     // ubar = dL/du(x): L = w sum omega^2 with omega_k(y) containing
     // (u_b(y + e_a) - u_b(y - e_a))/2 - (u_a(y + e_b) - u_a(y - e_b))/2
     double ub[3] = {0, 0, 0};
@@ -606,36 +860,33 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const S *__restrict__
     for (int k = 0; k < nv; ++k) {
         int a, b;
         vort_axes(D, k, a, b);
-        ub[b] += weight * ((double)vort[k * g.N + nb(g, x, y, z, a, -1)] - (double)vort[k * g.N + nb(g, x, y, z, a, 1)]);
-        ub[a] -= weight * ((double)vort[k * g.N + nb(g, x, y, z, b, -1)] - (double)vort[k * g.N + nb(g, x, y, z, b, 1)]);
+        ub[b] += weight * (n.at(vort + k * N, a, -1) - n.at(vort + k * N, a, 1));
+        ub[a] -= weight * (n.at(vort + k * N, b, -1) - n.at(vort + k * N, b, 1));
     }
-    double dr = 0.0, j[3] = {0, 0, 0};
+    const double ir = 1.0 / (double)rho[cell];
+    double uc[3] = {0, 0, 0};
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const double w = Lat<D>::w(i);
-        const double v = Storage<S>::full(f[(long long)i * g.N + cell], w) - w;
-        dr += v;
-#pragma unroll
-        for (int c = 0; c < D; ++c) j[c] += Lat<D>::c(i, c) * v;
-    }
-    const double r = 1.0 + dr;
-    double u[3];
-#pragma unroll
-    for (int c = 0; c < D; ++c) u[c] = (j[c] + (force ? 0.5 * (double)force[(long long)c * g.N + cell] : 0.0)) / r;
+    for (int c = 0; c < D; ++c) uc[c] = (double)u[c * N + cell];
     // du_c/df_i = (c_ic - u_c) / rho
     if (lam) {
+        double ubu = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) ubu += ub[c] * uc[c];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            double s = 0.0;
+            double s = -ubu;
 #pragma unroll
-            for (int c = 0; c < D; ++c) s += ub[c] * (Lat<D>::c(i, c) - u[c]);
-            lam[(long long)i * g.N + cell] += (T)(s / r);
+            for (int c = 0; c < D; ++c) {
+                if (Lat<D>::c(i, c) > 0) s += ub[c];
+                if (Lat<D>::c(i, c) < 0) s -= ub[c];
+            }
+            lam[(long long)i * N + cell] += (T)(s * ir);
         }
     }
     // du_c/dF_c = 1 / (2 rho) through the half-force shift
     if (force_grad) {
 #pragma unroll
-        for (int c = 0; c < D; ++c) force_grad[(long long)c * g.N + cell] += (float)(0.5 * ub[c] / r);
+        for (int c = 0; c < D; ++c) force_grad[(long long)c * N + cell] += (float)(0.5 * ub[c] * ir);
     }
 }
 
@@ -645,26 +896,33 @@ static hipError_t launch_diss_d(int dtype, const Grid &g, const void *f, const f
 {
     hipError_t e = ensure_scratch(g);
     if (e != hipSuccess) return e;
-    const dim3 grid((unsigned)((g.N + 255) / 256)), block(256);
+    const long long nflat = (g.N + 255) / 256;
+    if (nflat > 0x7fffffffLL || g.ny > 65535 || g.nz > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)nflat), block(256);
     if (dtype == 0)
-        hipLaunchKernelGGL((k_velocity<D, double>), grid, block, 0, s, g, (const double *)f, force, g_scratch.u);
+        hipLaunchKernelGGL((k_velocity<D, double>), grid, block, 0, s, g, (const double *)f, force, g_scratch.u,
+                           g_scratch.rho);
     else if (dtype == 1)
-        hipLaunchKernelGGL((k_velocity<D, float>), grid, block, 0, s, g, (const float *)f, force, g_scratch.u);
+        hipLaunchKernelGGL((k_velocity<D, float>), grid, block, 0, s, g, (const float *)f, force, g_scratch.u,
+                           g_scratch.rho);
     else if (dtype == 3)
-        hipLaunchKernelGGL((k_velocity<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, g_scratch.u);
+        hipLaunchKernelGGL((k_velocity<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, g_scratch.u,
+                           g_scratch.rho);
     else
         return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_vorticity<D>), grid, block, 0, s, g, g_scratch.u, g_scratch.vort, loss, weight);
+    const int bx = block_x(g.nx);
+    const dim3 sgrid((unsigned)((g.nx + bx - 1) / bx), (unsigned)g.ny, (unsigned)g.nz), sblock(bx);
+    double *part = loss ? g_scratch.part : nullptr;
+    hipLaunchKernelGGL((k_vorticity<D>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.vort, part, weight);
+    if (loss)
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (const double *)part, stencil_blocks(g), loss);
     if (lam || force_grad) {
         if (dtype == 0)
-            hipLaunchKernelGGL((k_diss_seed<D, double>), grid, block, 0, s, g, (const double *)f, force, g_scratch.vort,
-                               (double *)lam, weight, force_grad);
-        else if (dtype == 1)
-            hipLaunchKernelGGL((k_diss_seed<D, float>), grid, block, 0, s, g, (const float *)f, force, g_scratch.vort,
-                               (float *)lam, weight, force_grad);
+            hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.rho,
+                               g_scratch.vort, (double *)lam, weight, force_grad);
         else
-            hipLaunchKernelGGL((k_diss_seed<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, g_scratch.vort,
-                               (float *)lam, weight, force_grad);
+            hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.rho,
+                               g_scratch.vort, (float *)lam, weight, force_grad);
     }
     return hipGetLastError();
 }

@@ -27,3 +27,31 @@ def perturbed_state(D, eps, rng, rho=None, u=None, direction=None):
     d = null_space_direction(D, rng) if direction is None else direction
     g = feq + eps * d * feq.max()
     return g, feq
+
+
+def unstream(g):
+    """The state f whose pull-streamed image is g: f_i(y) = g_i(y + c_i).
+
+    Streaming is a permutation (Eq. advection), so this builds lattices whose
+    pulled populations have a prescribed distance from equilibrium."""
+    D = g.ndim - 1
+    c, _ = oracle.lattice(D)
+    out = np.empty_like(g)
+    for i in range(c.shape[0]):
+        shift = tuple(-int(c[i, a]) for a in reversed(range(D)))
+        out[i] = np.roll(g[i], shift, axis=tuple(range(D)))
+    return out
+
+
+def three_regime_state(D, shape, seed):
+    """A lattice whose pulled cells fall, about a third each, inside the gate
+    (max|x| < 1e-3), in the small-departure band (1e-3 <= max|x| < 5e-3) and
+    far from equilibrium (max|x| up to ~0.06): per-cell relative amplitudes
+    2e-4, 1.5e-3 and 3e-2 on an equilibrium with random rho and u."""
+    rng = np.random.default_rng(seed)
+    u = 0.03 * rng.standard_normal((D,) + tuple(shape))
+    rho = 1 + 0.01 * rng.standard_normal(tuple(shape))
+    g = oracle.init_equilibrium(rho, u)
+    amp = rng.choice([2e-4, 1.5e-3, 3e-2], size=tuple(shape))
+    g = g * (1 + amp * rng.uniform(-1, 1, g.shape))
+    return unstream(g)

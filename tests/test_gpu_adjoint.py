@@ -14,6 +14,7 @@ import torch
 import oracle
 from oracle import torch_ref as TR
 from paper_2203_12946_amd import workloads as W
+from tests._states import three_regime_state
 
 pytestmark = pytest.mark.gpu
 
@@ -76,6 +77,42 @@ def test_adjoint_step_matches_reference_vjp(es, D, shape, mode, dtype):
     got = out.double().cpu().numpy()
     err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
     _log(f"[vjp {lat} {mode} {dtype}] max rel err = {err:.3e}")
+    assert err < (1e-11 if dtype == "f64" else 1e-4)
+
+
+def _max_abs_x(f0):
+    """max_i |x_i| per pulled cell, from the FP64 reference."""
+    g = TR.stream(_t(f0))
+    rho, u = TR.moments(g)
+    x = TR.equilibrium(rho, u) / g - 1
+    return x.abs().max(0).values.numpy().ravel()
+
+
+@pytest.mark.parametrize("mode", ["higher", "lower"])
+@pytest.mark.parametrize("D,shape,seed", [(2, (16, 20), 5), (3, (6, 7, 9), 3)])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_step_all_regimes(es, D, shape, seed, mode, dtype):
+    """Gated cells, cells on the power-series evaluation of the path-length
+    sums, and cells on the exact rationals, in one lattice."""
+    lat = "D2Q9" if D == 2 else "D3Q27"
+    f0 = three_regime_state(D, shape, seed)
+    m = _max_abs_x(f0)
+    series_bound = 5e-3 if dtype == "f64" else 2e-2
+    # no cell near the gate, where FP32 and FP64 could branch differently
+    assert not np.any(np.abs(m / 1e-3 - 1) < 0.02)
+    frac = [np.mean(m < 1e-3), np.mean((m >= 1e-3) & (m < series_bound)), np.mean(m >= series_bound)]
+    assert min(frac) > 0.2, frac
+    tau = 2e-3
+    lam = np.random.default_rng(seed + 1).standard_normal(f0.shape)
+    ref, _ = _ref_vjp(f0, lam, tau, mode)
+    s = es.Solver(lat, shape, dtype=dtype, mode=mode)
+    out = s.empty_adjoint()
+    s.adjoint_step(_t(f0).to(s.storage_dtype).cuda(), _t(lam).to(s.compute_dtype).cuda(), out, tau)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    _log(f"[vjp regimes {lat} {mode} {dtype}] gated/series/exact = {frac[0]:.2f}/{frac[1]:.2f}/{frac[2]:.2f}, "
+         f"max rel err = {err:.3e}")
     assert err < (1e-11 if dtype == "f64" else 1e-4)
 
 
