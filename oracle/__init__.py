@@ -26,7 +26,7 @@ _SRC = _HERE / "eselbm_oracle.c"
 _LIB_PATH = _HERE / "liboracle.so"
 _lib = None
 
-MODES = {"higher": 0, "bgk": 1, "lower": 2}
+MODES = {"higher": 0, "bgk": 1, "lower": 2, "elbm": 3, "iterate1": 4}
 
 
 def build() -> pathlib.Path:
@@ -126,7 +126,7 @@ def cell_moments(D: int, f):
 
 
 _DETAIL_KEYS = ("alpha", "alpha_lower", "h", "a", "b", "c", "a1", "b1", "c1", "a2",
-                "x_min", "x_absmax", "gated", "guarded", "alpha_unguarded")
+                "x_min", "x_absmax", "gated", "guarded", "alpha_unguarded", "no_root")
 
 
 def path_length(g, feq, beta: float, mode: str = "higher") -> dict:
@@ -134,13 +134,14 @@ def path_length(g, feq, beta: float, mode: str = "higher") -> dict:
     lib = _load()
     g = _f64(g)
     feq = _f64(feq)
-    det = np.zeros(15)
+    det = np.zeros(16)
     rc = lib.orc_path_length(g.size, _dp(g), _dp(feq), float(beta), MODES[mode], _dp(det))
     if rc != 0:
         raise OracleError("non-positive or non-finite population")
     d = dict(zip(_DETAIL_KEYS, det.tolist()))
     d["gated"] = bool(d["gated"])
     d["guarded"] = bool(d["guarded"])
+    d["no_root"] = bool(d["no_root"])
     return d
 
 
@@ -191,15 +192,15 @@ def step(f, nsteps: int, tau: float, mode: str = "higher", force=None,
          want_alpha: bool = False):
     """Run nsteps periodic pull-stream + collide steps; returns the new state.
 
-    With ``want_alpha`` returns ``(state, alpha_field, (n_gated, n_guarded))``
-    for the last step.  ``force`` is a [D, ...grid] body-force density.
+    With ``want_alpha`` returns ``(state, alpha_field, (n_gated, n_guarded,
+    n_no_root))`` for the last step.  ``force`` is a [D, ...grid] body-force density.
     """
     lib = _load()
     f = _f64(f)
     D, nx, ny, nz = _grid(f)
     out = np.empty_like(f)
     alpha = np.empty(f.shape[1:]) if want_alpha else None
-    counts = np.zeros(2, dtype=np.int64)
+    counts = np.zeros(3, dtype=np.int64)
     F = None if force is None else _f64(force)
     if F is not None and F.shape != (D,) + f.shape[1:]:
         raise ValueError("force must be [D, ...grid]")
@@ -211,7 +212,7 @@ def step(f, nsteps: int, tau: float, mode: str = "higher", force=None,
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     if want_alpha:
-        return out, alpha, (int(counts[0]), int(counts[1]))
+        return out, alpha, (int(counts[0]), int(counts[1]), int(counts[2]))
     return out
 
 

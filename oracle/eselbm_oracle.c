@@ -31,7 +31,10 @@
 
 #define ORC_QMAX 27
 
-enum { ORC_HIGHER = 0, ORC_BGK = 1, ORC_LOWER = 2 };
+enum { ORC_HIGHER = 0, ORC_BGK = 1, ORC_LOWER = 2, ORC_ELBM = 3, ORC_ITERATE1 = 4 };
+
+double orc_alpha_elbm(int Q, const double *g, const double *feq);
+double orc_alpha_iterate1(int Q, const double *g, const double *feq);
 
 /* ---------------------------------------------------------------------
  * Lattice: D1Q3 weights w(0) = 2/3, w(+-1) = 1/6 and their tensor
@@ -107,10 +110,20 @@ void orc_cell_moments(int D, const double *f, double *rho, double *u)
  * Path length alpha for one cell (Sec. IV, App. C, App. D).
  *
  * g: pre-collision populations, feq: their equilibrium, beta from tau.
+ * mode: ORC_HIGHER (alpha_Higher), ORC_BGK (alpha = 2), ORC_LOWER
+ * (alpha_Lower), ORC_ELBM (the converged root of the mirror condition,
+ * Sec. III) or ORC_ITERATE1 (one Newton step of it from alpha_Lower,
+ * Sec. V C).  All but ORC_BGK use the near-equilibrium gate and the
+ * positivity guard of App. D.  A mirror path length lies in (1, alpha*),
+ * alpha* = -1/x_min being the edge of the polytope of positivity; where the
+ * ELBM root does not exist (the mirror leaves the polytope, Sec. III) or the
+ * Newton step lands outside that interval, the two modes keep alpha_Lower,
+ * the closed-form path length that never produces entropy (Sec. IV A).
  * detail (may be NULL) receives
  *   [0] alpha  [1] alpha_Lower  [2] h  [3] a  [4] b  [5] c
  *   [6] a1     [7] b1           [8] c1 [9] a2 [10] x_min [11] max|x|
  *   [12] gated (0/1)  [13] guard applied (0/1)  [14] alpha before guard
+ *   [15] no valid mirror path length, alpha_Lower kept (0/1, ELBM modes)
  * Return value: 0, or -1 if some g_i <= 0 or is not finite (x undefined).
  * ------------------------------------------------------------------- */
 static double conj_root(double a, double b, double c)
@@ -124,7 +137,7 @@ int orc_path_length(int Q, const double *g, const double *feq, double beta,
                     int mode, double *detail)
 {
     double x[ORC_QMAX];
-    double out[15];
+    double out[16];
     memset(out, 0, sizeof(out));
     if (Q < 1 || Q > ORC_QMAX) return -1;
     for (int i = 0; i < Q; ++i) {
@@ -169,6 +182,14 @@ int orc_path_length(int Q, const double *g, const double *feq, double beta,
         out[8] = c1;
         if (mode == ORC_LOWER) {
             alpha = aL;
+        } else if (mode == ORC_ELBM || mode == ORC_ITERATE1) {
+            /* The mirror condition H[f + alpha (feq - f)] = H[f]: its root
+             * (ELBM) or one Newton step towards it from alpha_Lower. */
+            alpha = mode == ORC_ELBM ? orc_alpha_elbm(Q, g, feq) : orc_alpha_iterate1(Q, g, feq);
+            if (!(alpha > 1.0 && alpha < -1.0 / xmin)) {
+                alpha = aL; /* no valid mirror path length */
+                out[15] = 1.0;
+            }
         } else {
             /* Higher-order coefficients b, c (Eq. qaud_tight_coeff) and
              * a2 (Eq. a2def); h is the positive root of H_2 (Eq. gaplhah0). */
@@ -319,6 +340,8 @@ double orc_alpha_iterate1(int Q, const double *g, const double *feq)
         c1 += g[i] * 2.0 * x[i] * x[i] / (2.0 + x[i]);
     }
     double a0 = conj_root(a1, b1, c1);
+    for (int i = 0; i < Q; ++i)
+        if (!(1.0 + a0 * x[i] > 0.0)) return NAN; /* alpha_Lower beyond the polytope */
     return a0 - orc_dH_mirror(Q, g, feq, a0) / dH_mirror_prime(Q, g, x, a0);
 }
 
@@ -336,7 +359,8 @@ static long long wrap(long long v, long long n) { v %= n; return v < 0 ? v + n :
  *   f* += feq(rho, u + F/rho) - feq(rho, u)  (the paper has no forcing;
  *   this is the reading used for the forced workload).
  * alpha_out: NULL or per-cell alpha of the last step.
- * counts: NULL or [gated, guarded] counts of the last step.
+ * counts: NULL or [gated, guarded, alpha_Lower fallback of the ELBM modes]
+ *   counts of the last step.
  * Returns 0, or -1 on a non-positive / non-finite pre-collision population.
  */
 int orc_step(int D, int nx, int ny, int nz, const double *f_in, double *f_out, int nsteps,
@@ -352,16 +376,16 @@ int orc_step(int D, int nx, int ny, int nz, const double *f_in, double *f_out, i
     if (!cur || !nxt) { free(cur); free(nxt); return -2; }
     memcpy(cur, f_in, sizeof(double) * Q * N);
     int bad = 0;
-    long long ngated = 0, nguard = 0;
+    long long ngated = 0, nguard = 0, nnoroot = 0;
     for (int s = 0; s < nsteps; ++s) {
         int last = (s == nsteps - 1);
-        long long sg = 0, sd = 0;
-#pragma omp parallel for collapse(2) reduction(+ : sg, sd) reduction(| : bad)
+        long long sg = 0, sd = 0, sn = 0;
+#pragma omp parallel for collapse(2) reduction(+ : sg, sd, sn) reduction(| : bad)
         for (int z = 0; z < nz; ++z) {
             for (int y = 0; y < ny; ++y) {
                 for (int xx = 0; xx < nx; ++xx) {
                     long long cell = ((long long)z * ny + y) * nx + xx;
-                    double g[ORC_QMAX], feq[ORC_QMAX], det[15];
+                    double g[ORC_QMAX], feq[ORC_QMAX], det[16];
                     for (int i = 0; i < Q; ++i) {
                         long long sx = wrap(xx - c[3 * i + 0], nx);
                         long long sy = wrap(y - c[3 * i + 1], ny);
@@ -388,18 +412,19 @@ int orc_step(int D, int nx, int ny, int nz, const double *f_in, double *f_out, i
                         if (alpha_out) alpha_out[cell] = alpha;
                         sg += det[12] > 0.0;
                         sd += det[13] > 0.0;
+                        sn += det[15] > 0.0;
                     }
                 }
             }
         }
         if (bad) break;
-        if (last) { ngated = sg; nguard = sd; }
+        if (last) { ngated = sg; nguard = sd; nnoroot = sn; }
         double *t = cur; cur = nxt; nxt = t;
     }
     if (!bad) memcpy(f_out, cur, sizeof(double) * Q * N);
     free(cur);
     free(nxt);
-    if (counts) { counts[0] = ngated; counts[1] = nguard; }
+    if (counts) { counts[0] = ngated; counts[1] = nguard; counts[2] = nnoroot; }
     return bad ? -1 : 0;
 }
 

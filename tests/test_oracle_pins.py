@@ -443,7 +443,7 @@ def test_equilibrium_input_is_fixed_point():
     for D in (2, 3):
         feq = oracle.equilibrium(D, 1.1, [0.04, -0.03, 0.02][:D])
         f = feq.reshape((-1,) + (1,) * D)
-        out, alpha, (ng, nd) = oracle.step(f, 1, 0.01, want_alpha=True)
+        out, alpha, (ng, nd, _) = oracle.step(f, 1, 0.01, want_alpha=True)
         np.testing.assert_allclose(out.ravel(), feq, rtol=1e-15, atol=0)
         assert alpha.ravel()[0] == 2.0 and ng == 1 and nd == 0
 
@@ -555,3 +555,79 @@ def test_light_cone_block_reproduces_full_grid():
         blk = oracle.light_cone_block(f, center, k)
         out = oracle.step(blk, k, 3e-5)
         np.testing.assert_array_equal(out[:, k, k], full[:, center[0], center[1]])
+
+
+# --------------------------------------------------------------------------
+# Iterative ELBM modes of the whole step (Sec. III mirror condition, Sec. V C)
+# --------------------------------------------------------------------------
+def _mixed_lattice(D, shape, seed, sigma=1.2):
+    """Pulled cells near equilibrium (gated), moderately off it, and far off
+    it (log-normal populations, often without a mirror root), un-streamed so
+    that one step collides exactly these cells."""
+    from tests._states import unstream
+    rng = np.random.default_rng(seed)
+    u = 0.03 * rng.standard_normal((D,) + shape)
+    rho = 1 + 0.01 * rng.standard_normal(shape)
+    g = oracle.init_equilibrium(rho, u)
+    kind = rng.integers(0, 3, size=shape)
+    pert = np.where(kind == 0, 2e-4 * rng.uniform(-1, 1, g.shape),
+                    np.where(kind == 1, 0.05 * rng.uniform(-1, 1, g.shape), 0.0))
+    g = g * (1 + pert)
+    far = np.exp(rng.normal(0, sigma, g.shape))
+    g = np.where(kind == 2, g * far, g)
+    return unstream(g)
+
+
+@pytest.mark.parametrize("mode", ["elbm", "iterate1"])
+@pytest.mark.parametrize("D,shape", [(2, (12, 14)), (3, (4, 5, 6))])
+def test_mirror_modes_whole_step(D, shape, mode):
+    """One lattice step with the mirror-condition path length: alpha is the
+    root of H[f + alpha (feq - f)] = H[f] (ELBM) or one Newton step to it from
+    alpha_Lower (Iterate1) in every ungated cell, 2 in gated cells, and
+    alpha_Lower where that is not a path length in (1, -1/x_min) (no mirror
+    root, or a step outside the polytope); mass and momentum are conserved,
+    every population stays positive, and in ELBM mode the per-cell entropy
+    change of the step is <= 0 (Sec. III: the mirror is isentropic and
+    beta < 1 adds dissipation; Sec. IV A: alpha_Lower never produces
+    entropy)."""
+    f = _mixed_lattice(D, shape, 40 + D)
+    tau = 2e-3
+    beta = 1 / (2 * tau + 1)
+    out, alpha, (ng, nd, nn) = oracle.step(f, 1, tau, mode=mode, want_alpha=True)
+    from oracle import torch_ref as TR
+    import torch
+    g = TR.stream(torch.from_numpy(f)).numpy()
+    Q = g.shape[0]
+    gc = g.reshape(Q, -1)
+    ac = alpha.ravel()
+    n_root = n_edge = 0
+    for k in range(gc.shape[1]):
+        gk = gc[:, k]
+        r, uu = oracle.cell_moments(D, gk)
+        feq = oracle.equilibrium(D, r, uu)
+        x = feq / gk - 1
+        if np.max(np.abs(x)) < 1e-3:
+            assert ac[k] == 2.0
+            continue
+        ref = oracle.alpha_elbm(gk, feq) if mode == "elbm" else oracle.alpha_iterate1(gk, feq)
+        amax = -1 / (beta * x.min())
+        if np.isfinite(ref) and 1 < ref < -1 / x.min():
+            n_root += 1
+            exp_a = ref if ref <= amax else (1 + amax) / 2
+            assert ac[k] == exp_a
+            if mode == "elbm":
+                assert abs(oracle.dH_mirror(gk, feq, ac[k])) < 1e-13 * np.sum(gk)
+        else:
+            n_edge += 1
+            aL = oracle.path_length(gk, feq, beta, "lower")["alpha_lower"]
+            assert ac[k] == (aL if aL <= amax else (1 + amax) / 2)
+        if mode == "elbm":
+            assert oracle.dH_step(gk, feq, ac[k], beta) <= 1e-15 * np.sum(gk)
+    assert n_root > 10 and n_edge > 3 and nn == n_edge and ng > 5
+    assert np.all(out > 0)
+    for a in range(D + 1):
+        c, _ = oracle.lattice(D)
+        wts = np.ones(Q) if a == 0 else c[:, a - 1].astype(float)
+        m_in = np.tensordot(wts, f, axes=(0, 0)).sum()
+        m_out = np.tensordot(wts, out, axes=(0, 0)).sum()
+        assert abs(m_in - m_out) < 1e-12 * np.abs(f).sum()
