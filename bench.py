@@ -4,8 +4,10 @@ Headline: D3Q27 ESELBM (alpha_Higher) on the 256^3 periodic Taylor-Green
 vortex at Re 1600 with seeded velocity noise, FP32 storage and arithmetic.
 One "step" is one full pull-stream + collide pass over the grid (one kernel
 launch).  Reported beside it, on the same workload and GPU: FP64 storage,
-FP16-shifted storage, plain BGK (alpha = 2), and the adjoint/forward time of
-the 128^3 forced D3Q27 rollout with checkpointing.
+FP16-shifted storage, plain BGK (alpha = 2), alpha_Lower, the iterative
+ELBM path length and its one-step alpha_Iterate1 (the root search the
+closed form replaces), and the adjoint/forward time of the 128^3 forced
+D3Q27 rollout with checkpointing.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
@@ -250,7 +252,8 @@ def main():
     variants = {}
     if not args.no_variants:
         for dtype, mode, bpc in (("f64", "higher", 432), ("f32s", "higher", 216), ("f16s", "higher", 108),
-                                 ("f32", "bgk", 216), ("f64", "bgk", 432), ("f32", "lower", 216)):
+                                 ("f32", "bgk", 216), ("f64", "bgk", 432), ("f32", "lower", 216),
+                                 ("f32", "elbm", 216), ("f32", "iterate1", 216)):
             _log(f"bench: {dtype} {mode}")
             r = time_forward(es, torch, W, wl, dtype, mode, max(20, args.steps // 2), 5, rho_d, u_d)
             gbs = bpc * cells / (r["kernel_ms"] * 1e-3) / 1e9
@@ -258,6 +261,11 @@ def main():
                 mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 4),
                 hbm_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_cell=bpc,
                 n_gated=r["stats"]["n_gated"], n_exact=r["stats"]["n_exact"])
+            if mode in ("elbm", "iterate1"):
+                ung = max(1, r["stats"]["n_cells"] - r["stats"]["n_gated"])
+                variants[f"{dtype}_{mode}"].update(
+                    newton_per_ungated_cell=round(r["stats"]["n_newton"] / ung, 3),
+                    n_mirror_fallback=r["stats"]["n_mirror_fallback"])
             _log(f"bench: {dtype} {mode} {r['mlups']:.0f} MLUPS")
     del rho_d, u_d
     torch.cuda.empty_cache()

@@ -38,7 +38,7 @@
  *
  * Ownership: every buffer passed in is device memory owned by the caller.
  * The library never frees caller memory.  It owns only the handle and a
- * small (< 4 KiB) device block of diagnostic accumulators, which
+ * small (8 KiB) device block of diagnostic accumulators, which
  * eselbm_create allocates and eselbm_destroy frees.
  *
  * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
@@ -65,11 +65,29 @@ typedef struct eselbm_ctx *eselbm_handle;
 
 typedef enum { ESELBM_D2Q9 = 0, ESELBM_D3Q27 = 1 } eselbm_lattice;
 typedef enum { ESELBM_F64 = 0, ESELBM_F32 = 1, ESELBM_F16_SHIFTED = 2, ESELBM_F32_SHIFTED = 3 } eselbm_dtype;
-/* HIGHER: alpha_Higher (Sec. IV B, App. D), the default.
- * BGK:    alpha = 2 everywhere, no gate or guard (standard LBGK, Sec. II).
- * LOWER:  alpha_Lower (Sec. IV A, Eq. alphaLowerSoln) with the same gate
- *         and guard. */
-typedef enum { ESELBM_MODE_HIGHER = 0, ESELBM_MODE_BGK = 1, ESELBM_MODE_LOWER = 2 } eselbm_mode;
+/* HIGHER:   alpha_Higher (Sec. IV B, App. D), the default.
+ * BGK:      alpha = 2 everywhere, no gate or guard (standard LBGK, Sec. II).
+ * LOWER:    alpha_Lower (Sec. IV A, Eq. alphaLowerSoln) with the same gate
+ *           and guard.
+ * ELBM:     the iterative ELBM path length: the non-trivial root of
+ *           H[f + alpha (f^eq - f)] = H[f] (Sec. III, Eq. entropy_conserve,
+ *           Eq. deltaH_) on (1, -1/x_min), by Newton iteration from
+ *           alpha_Lower with bisection safeguard, converged to a relative
+ *           step of 1e-5 (single precision) or 1e-9 (double).
+ * ITERATE1: one Newton step of that condition from alpha_Lower
+ *           (alpha_Iterate1, Sec. V C).
+ * ELBM and ITERATE1 use the gate and guard of App. D; where their result is
+ * not a mirror path length in (1, -1/x_min) (no root: the mirror state
+ * leaves the polytope of positivity, Sec. III; or a Newton step outside
+ * that interval) the cell keeps alpha_Lower.  They are comparison modes of
+ * the forward step: eselbm_adjoint_step rejects them. */
+typedef enum {
+    ESELBM_MODE_HIGHER = 0,
+    ESELBM_MODE_BGK = 1,
+    ESELBM_MODE_LOWER = 2,
+    ESELBM_MODE_ELBM = 3,
+    ESELBM_MODE_ITERATE1 = 4
+} eselbm_mode;
 typedef enum {
     ESELBM_OK = 0,
     ESELBM_E_ARG = 1,          /* invalid argument; nothing was enqueued */
@@ -95,18 +113,21 @@ typedef enum {
  *             pulled populations.
  *   n_alpha_lt2  cells with alpha < 2.
  *   n_exact   cells whose path length was evaluated with the exact rational
- *             sums (single precision evaluates cells with all |x_i| < 0.02
- *             through truncated power series of the same sums; double
- *             precision always uses the exact sums).
+ *             sums (cells with all |x_i| below 0.02 in single precision and
+ *             0.005 in double are evaluated through truncated power series
+ *             of the same sums, accurate to the rounding of the type).
+ *   n_newton  ELBM and ITERATE1 modes: Newton iterations summed over cells.
+ *   n_mirror_fallback  ELBM and ITERATE1 modes: cells that kept alpha_Lower.
  */
 typedef struct {
     double mass, mom[3], kinetic, H;
     double alpha_min, alpha_max, alpha_mean;
     long long n_cells, n_gated, n_guard, n_nonpos, n_alpha_lt2, n_exact;
+    long long n_newton, n_mirror_fallback;
 } eselbm_stats;
 
 /* Creates a solver for an nx * ny * nz periodic grid (nz must be 1 for
- * D2Q9).  Allocates the < 4 KiB accumulator block on the current device.
+ * D2Q9).  Allocates the 8 KiB accumulator block on the current device.
  * Errors: ESELBM_E_ARG for a NULL out, dims < 1, unknown lattice or dtype,
  * or a grid whose state does not fit a 63-bit index; ESELBM_E_UNSUPPORTED
  * for ny or nz above 65535 (the step launches one block row per (y, z)). */
@@ -128,6 +149,13 @@ eselbm_status eselbm_set_stats(eselbm_handle h, int enable);
  * disables it.  Cells that were not collided receive NaN.  Debug and
  * parity use only. */
 eselbm_status eselbm_set_alpha_field(eselbm_handle h, void *alpha);
+
+/* Registers a device buffer of n_cells compute-type values that receives
+ * the per-cell subgrid viscosity correction of the last step of each
+ * eselbm_step call, nu_T = theta (2 - alpha) / (2 alpha beta) with
+ * theta = 1/3 (Sec. VII, Eq. nuT): positive where alpha < 2.  NULL disables
+ * it.  Cells that were not collided receive NaN. */
+eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut);
 
 /* Registers a body-force density F (device float, [D][nz][ny][nx]) added
  * after the collision as f* += feq(rho, u + F/rho) - feq(rho, u) (exact
@@ -173,7 +201,8 @@ eselbm_status eselbm_moments(eselbm_handle h, const void *f, double *rho, double
  *             Must not alias lam_next.
  *   force_grad: NULL, or with a force registered, a device float
  *             [D][cells] buffer to which dL/dF of this step is ADDED.
- * Supported for ESELBM_F32 and ESELBM_F64 in modes HIGHER, LOWER and BGK. */
+ * Supported for ESELBM_F32, ESELBM_F32_SHIFTED and ESELBM_F64 in modes
+ * HIGHER, LOWER and BGK (ESELBM_E_UNSUPPORTED otherwise). */
 eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next,
                                   void *lam_n, double tau, void *force_grad, void *stream);
 

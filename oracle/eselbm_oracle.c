@@ -264,14 +264,18 @@ double orc_H(int D, long long ncells, const double *f)
 }
 
 /* H[f + alpha beta (feq - f)] - H[f] for one cell, Eq. deltaH3:
- * <f, (1 + xh) log(1 + xh)> - alpha beta <f, x log(1 + x)>, xh = alpha beta x. */
+ * <f, (1 + xh) log(1 + xh)> - alpha beta <f, x log(1 + x)>, xh = alpha beta x.
+ * The first sum contains alpha beta <f, x>, which App. A shows to be zero
+ * (<f, x> = sum_i (feq_i - f_i) = rho - rho); it is dropped term by term,
+ * <f, (1 + xh) log(1 + xh) - xh>, so that its rounding (about 1e-16 rho,
+ * against a change of order <f, x^2>) does not enter the result. */
 double orc_dH_step(int Q, const double *g, const double *feq, double alpha, double beta)
 {
     double s1 = 0.0, s2 = 0.0;
     for (int i = 0; i < Q; ++i) {
         double x = feq[i] / g[i] - 1.0;
         double xh = alpha * beta * x;
-        s1 += g[i] * (1.0 + xh) * log1p(xh);
+        s1 += g[i] * ((1.0 + xh) * log1p(xh) - xh);
         s2 += g[i] * x * log1p(x);
     }
     return s1 - alpha * beta * s2;

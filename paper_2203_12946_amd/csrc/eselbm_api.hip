@@ -21,6 +21,7 @@ struct eselbm_ctx {
     int have_stats;
     int device;
     void *alpha_field;
+    void *nut_field;
     const float *force;
     const void *last_out;  // output state of the last statistics-enabled step
     DevStats *dev_stats;   // kStatSlots slots
@@ -90,7 +91,7 @@ eselbm_status eselbm_destroy(eselbm_handle h)
 eselbm_status eselbm_set_mode(eselbm_handle h, int mode)
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_set_mode: NULL handle");
-    if (mode < ESELBM_MODE_HIGHER || mode > ESELBM_MODE_LOWER) return fail(ESELBM_E_ARG, "eselbm_set_mode: unknown mode");
+    if (mode < ESELBM_MODE_HIGHER || mode > ESELBM_MODE_ITERATE1) return fail(ESELBM_E_ARG, "eselbm_set_mode: unknown mode");
     h->mode = mode;
     return ESELBM_OK;
 }
@@ -106,6 +107,13 @@ eselbm_status eselbm_set_alpha_field(eselbm_handle h, void *alpha)
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_set_alpha_field: NULL handle");
     h->alpha_field = alpha;
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_nut_field: NULL handle");
+    h->nut_field = nut;
     return ESELBM_OK;
 }
 
@@ -149,8 +157,9 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
         sa.beta = 1.0 / (2.0 * tau + 1.0);
         sa.force = h->force;
         sa.alpha_out = last ? h->alpha_field : nullptr;
+        sa.nut_out = last ? h->nut_field : nullptr;
         sa.stats = (last && h->stats_on) ? h->dev_stats : nullptr;
-        const bool diag = sa.alpha_out != nullptr || sa.stats != nullptr;
+        const bool diag = sa.alpha_out != nullptr || sa.nut_out != nullptr || sa.stats != nullptr;
         if (sa.stats) {
             hipError_t e = launch_reset_stats(h->dev_stats, s);
             if (e != hipSuccess) return hip_fail(e, "eselbm_step: reset");
@@ -201,6 +210,8 @@ eselbm_status eselbm_alpha_stats(eselbm_handle h, eselbm_stats *out, int with_H,
         out->n_nonpos += (long long)d.n_nonpos;
         out->n_alpha_lt2 += (long long)d.n_lt2;
         out->n_exact += (long long)d.n_exact;
+        out->n_newton += (long long)d.n_iter;
+        out->n_mirror_fallback += (long long)d.n_fallback;
         mn = d.alpha_min_bits < mn ? d.alpha_min_bits : mn;
         mx = d.alpha_max_bits > mx ? d.alpha_max_bits : mx;
     }
@@ -231,6 +242,8 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: tau must be finite and > 0");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: F16 storage has no adjoint");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: force_grad without a registered force");
+    if (h->mode == ESELBM_MODE_ELBM || h->mode == ESELBM_MODE_ITERATE1)
+        return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the mirror-condition modes");
     AdjArgs a;
     a.fn = f_n;
     a.lam_next = lam_next;

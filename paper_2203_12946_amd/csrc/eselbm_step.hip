@@ -49,39 +49,40 @@ __device__ inline unsigned long long wave_max_u64(unsigned long long v)
 struct LaneStats {
     double mass = 0, mom[3] = {0, 0, 0}, ke = 0, asum = 0;
     unsigned long long amin = 0x7FF0000000000000ull, amax = 0;
-    unsigned long long n = 0, gated = 0, guard = 0, nonpos = 0, lt2 = 0, exact = 0;
+    unsigned long long n = 0, gated = 0, guard = 0, nonpos = 0, lt2 = 0, exact = 0, iters = 0, fallback = 0;
 };
 
 __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
 {
+    constexpr int NU = 8;  // counters
     __shared__ double red_d[4][7];
-    __shared__ unsigned long long red_u[4][8];
+    __shared__ unsigned long long red_u[4][NU + 2];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     double v[7] = {s.mass, s.mom[0], s.mom[1], s.mom[2], s.ke, s.asum, 0.0};
-    unsigned long long c[6] = {s.n, s.gated, s.guard, s.nonpos, s.lt2, s.exact};
+    unsigned long long c[NU] = {s.n, s.gated, s.guard, s.nonpos, s.lt2, s.exact, s.iters, s.fallback};
 #pragma unroll
     for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
 #pragma unroll
-    for (int k = 0; k < 6; ++k) c[k] = wave_sum(c[k]);
+    for (int k = 0; k < NU; ++k) c[k] = wave_sum(c[k]);
     const unsigned long long mn = wave_min_u64(s.amin), mx = wave_max_u64(s.amax);
     if (lane == 0) {
         for (int k = 0; k < 6; ++k) red_d[wid][k] = v[k];
-        for (int k = 0; k < 6; ++k) red_u[wid][k] = c[k];
-        red_u[wid][6] = mn;
-        red_u[wid][7] = mx;
+        for (int k = 0; k < NU; ++k) red_u[wid][k] = c[k];
+        red_u[wid][NU] = mn;
+        red_u[wid][NU + 1] = mx;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
         const int nw = (blockDim.x + 63) >> 6;
         DevStats *st = slot;
         double t[6] = {0, 0, 0, 0, 0, 0};
-        unsigned long long u[6] = {0, 0, 0, 0, 0, 0};
-        unsigned long long tmn = red_u[0][6], tmx = red_u[0][7];
+        unsigned long long u[NU] = {0, 0, 0, 0, 0, 0, 0, 0};
+        unsigned long long tmn = red_u[0][NU], tmx = red_u[0][NU + 1];
         for (int w = 0; w < nw; ++w) {
             for (int k = 0; k < 6; ++k) t[k] += red_d[w][k];
-            for (int k = 0; k < 6; ++k) u[k] += red_u[w][k];
-            tmn = red_u[w][6] < tmn ? red_u[w][6] : tmn;
-            tmx = red_u[w][7] > tmx ? red_u[w][7] : tmx;
+            for (int k = 0; k < NU; ++k) u[k] += red_u[w][k];
+            tmn = red_u[w][NU] < tmn ? red_u[w][NU] : tmn;
+            tmx = red_u[w][NU + 1] > tmx ? red_u[w][NU + 1] : tmx;
         }
         atomicAdd(&st->mass, t[0]);
         atomicAdd(&st->mom[0], t[1]);
@@ -95,6 +96,8 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
         atomicAdd(&st->n_nonpos, u[3]);
         atomicAdd(&st->n_lt2, u[4]);
         atomicAdd(&st->n_exact, u[5]);
+        if (u[6]) atomicAdd(&st->n_iter, u[6]);
+        if (u[7]) atomicAdd(&st->n_fallback, u[7]);
         atomicMin(&st->alpha_min_bits, tmn);
         atomicMax(&st->alpha_max_bits, tmx);
     }
@@ -173,8 +176,14 @@ __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)
     conserve_moments<D, T>(d);
 }
 
+// The mirror-condition modes iterate over Q logarithms per Newton step:
+// they are ALU-bound, and their loop needs the registers of two waves per
+// SIMD.
+template <typename S, int MODE>
+constexpr int step_waves() { return is_mirror_mode(MODE) ? 2 : StepPolicy<S>::waves; }
+
 template <int D, typename S, int MODE, bool DIAG, bool FORCE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepPolicy<S>::waves))) void k_step(StepArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves<S, MODE>()))) void k_step(StepArgs a)
 {
     using T = typename Storage<S>::T;
     using Pol = StepPolicy<S>;
@@ -232,7 +241,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepPolicy<
         const bool ok = pos && abs_(drhoE) < E(1e30);
         const T rho = T(1) + drho;
         T alpha = T(0);
-        CellInfo info{0, 0, 0};
+        CellInfo info{0, 0, 0, 0, 0};
         T dd[Q];
         // the output is p + (ab + ab_lo) dd; where the policy asks for it,
         // alpha beta is a two-term sum so that its rounding to single
@@ -281,6 +290,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepPolicy<
 
         if (DIAG) {
             if (a.alpha_out) ((T *)a.alpha_out)[cell] = ok ? alpha : T(__builtin_nan(""));
+            // nu_T = theta (2 - alpha) / (2 alpha beta), theta = 1/3 (Eq. nuT)
+            if (a.nut_out)
+                ((T *)a.nut_out)[cell] = ok ? (T(2) - alpha) * rcp_(T(6) * alpha * beta) : T(__builtin_nan(""));
             if (ok) {
                 const double r = 1.0 + (double)drho;
                 ls.mass = r;
@@ -300,6 +312,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(StepPolicy<
                 ls.guard = info.guarded;
                 ls.lt2 = alpha < T(2);
                 ls.exact = info.exact;
+                ls.iters = info.iters;
+                ls.fallback = info.fallback;
             } else {
                 ls.nonpos = 1;
             }
@@ -336,6 +350,8 @@ static hipError_t launch_step_m(int mode, bool diag, const StepArgs &a, hipStrea
     case MODE_HIGHER: return launch_step_t<D, S, MODE_HIGHER>(diag, a, s);
     case MODE_BGK: return launch_step_t<D, S, MODE_BGK>(diag, a, s);
     case MODE_LOWER: return launch_step_t<D, S, MODE_LOWER>(diag, a, s);
+    case MODE_ELBM: return launch_step_t<D, S, MODE_ELBM>(diag, a, s);
+    case MODE_ITERATE1: return launch_step_t<D, S, MODE_ITERATE1>(diag, a, s);
     }
     return hipErrorInvalidValue;
 }

@@ -13,8 +13,10 @@ struct DevStats {
     double mass, mom[3], kinetic, alpha_sum, H, pad0;
     unsigned long long alpha_min_bits, alpha_max_bits;
     unsigned long long n_cells, n_gated, n_guard, n_nonpos, n_lt2, n_exact;
+    unsigned long long n_iter, n_fallback;  // mirror modes
+    unsigned long long pad1[14];
 };
-static_assert(sizeof(DevStats) == 128, "DevStats is one 128-byte line");
+static_assert(sizeof(DevStats) == 256, "DevStats is two 128-byte lines");
 constexpr int kStatSlots = 32;
 
 struct Grid {
@@ -29,6 +31,7 @@ struct StepArgs {
     double beta;
     const float *force;  // [D][N] or null
     void *alpha_out;     // [N] compute type or null
+    void *nut_out;       // [N] compute type or null: nu_T of Eq. nuT
     DevStats *stats;     // kStatSlots slots or null
 };
 

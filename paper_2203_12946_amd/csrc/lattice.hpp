@@ -133,7 +133,10 @@ __device__ inline T quot_(T j, T rho, T r)
     return fma_(r, fma_(-rho, u0, j), u0);
 }
 
-enum Mode { MODE_HIGHER = 0, MODE_BGK = 1, MODE_LOWER = 2 };
+enum Mode { MODE_HIGHER = 0, MODE_BGK = 1, MODE_LOWER = 2, MODE_ELBM = 3, MODE_ITERATE1 = 4 };
+
+// The two modes that take alpha from the mirror condition (Sec. III).
+__host__ __device__ constexpr bool is_mirror_mode(int m) { return m == MODE_ELBM || m == MODE_ITERATE1; }
 
 // ---------------------------------------------------------------------------
 // Entropic equilibrium, product form (Sec. II).  Per axis the D1Q3 factors
@@ -333,6 +336,7 @@ __device__ inline void moments_shifted(const T (&gt)[Lat<D>::Q], T &drho, T (&j)
 
 struct CellInfo {
     int gated, guarded, exact;  // exact: the exact rational path ran
+    int iters, fallback;        // mirror modes: Newton iterations; alpha_Lower kept
 };
 
 // Positive root of -a s^2 + b s - c = 0 in the conjugate form
@@ -430,7 +434,7 @@ __device__ inline T gval(int i, const T (&p)[Lat<D>::Q])
 // no Q-array of A is live.  One reciprocal per population serves c1 and c
 // together.  Returns alpha before the guard and x_min in xmin.
 template <int D, typename T, typename A, int MODE, bool SH>
-__device__ inline A alpha_exact(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], A beta, A &xmin)
+__device__ __attribute__((always_inline)) inline A alpha_exact(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], A beta, A &xmin)
 {
     constexpr int Q = Lat<D>::Q;
     A S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0;
@@ -480,13 +484,112 @@ __device__ inline A alpha_exact(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q]
     return higher_from_coeffs(aL, b1, Bp, C, M3, M4, M5, M6, beta);
 }
 
+// ---------------------------------------------------------------------------
+// The mirror condition of the iterative ELBM (Sec. III, Eq. entropy_conserve
+// and Eq. deltaH_), for the ELBM and Iterate1 modes:
+//   dH(a) = <g, (1 + a x) log(1 + a x)> - a <g, x log(1 + x)> = 0,
+// the non-trivial root on (1, a*), a* = -1/x_min (the mirror state's edge of
+// the polytope of positivity).  Since <g, x> = sum d = 0 the linear parts
+// cancel exactly, and
+//   dH(a)  = <g, phi(a x)> - a S,   phi(y) = (1 + y) log(1 + y) - y,
+//   dH'(a) = <d, log(1 + a x)> - S, S = <d, log(1 + x)>,
+// evaluated without the cancellation of the printed form: phi by its Taylor
+// series sum_{k>=2} (-1)^k y^k / (k (k-1)) where |y| < Y (truncated below
+// the rounding of the type there), by the closed form beyond.  dH is convex
+// with dH(0) = 0 and dH'(0) = -S < 0, so the root is unique; Newton from
+// alpha_Lower (Sec. V C) keeps a bracket [lo, hi] and bisects when a step
+// leaves it.
+// ---------------------------------------------------------------------------
+template <typename T>
+struct MirrorCfg;
+template <>
+struct MirrorCfg<float> {
+    static constexpr double Y = 0.25;   // series terms to y^12: remainder < 3e-8 relative
+    static constexpr int K = 12;
+    static constexpr double tol = 1e-5;  // |step| / alpha at which Newton stops
+    static constexpr int maxit = 30;
+};
+template <>
+struct MirrorCfg<double> {
+    static constexpr double Y = 0.05;   // series terms to y^13: remainder < 3e-18 relative
+    static constexpr int K = 13;
+    static constexpr double tol = 1e-9;
+    static constexpr int maxit = 60;
+};
+
+__device__ inline float log1p_(float v) { return log1pf(v); }
+__device__ inline double log1p_(double v) { return log1p(v); }
+
+// phi(y) = (1 + y) log(1 + y) - y given l = log(1 + y); both forms are
+// evaluated and one selected (no per-population branch in a wave)
+template <typename T>
+__device__ inline T phi_(T y, T l)
+{
+    constexpr int K = MirrorCfg<T>::K;
+    T s = T((K % 2 ? -1.0 : 1.0) / (K * (K - 1.0)));
+#pragma unroll
+    for (int k = K - 1; k >= 2; --k) s = fma_(s, y, T((k % 2 ? -1.0 : 1.0) / (k * (k - 1.0))));
+    const T series = s * y * y, closed = fma_(T(1) + y, l, -y);
+    return abs_(y) < T(MirrorCfg<T>::Y) ? series : closed;
+}
+
+// alpha from the mirror condition in the arithmetic type A: the converged
+// root (FULL, the ELBM mode) or one Newton step from alpha_Lower (the
+// Iterate1 mode).  Returns alpha_Lower, with info.fallback set, where the
+// result is not a mirror path length in (1, a*): no root (the mirror leaves
+// the polytope) or a step outside the interval.
+template <int D, typename T, typename A, bool SH, bool FULL>
+__device__ __attribute__((always_inline)) inline A mirror_alpha(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], A aL, A xmin, CellInfo &info)
+{
+    constexpr int Q = Lat<D>::Q;
+    auto xof = [&](int i) { return A(d[i]) * rcp_(A(gval<D, T, SH>(i, p))); };
+    A S = A(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) S = fma_(A(d[i]), log1p_(xof(i)), S);
+    const A astar = A(-1) * rcp_(xmin);
+    A lo = A(1), hi = astar;
+    const bool start_ok = aL > lo && aL < hi;
+    A a = start_ok ? aL : A(0.5) * (lo + hi);
+    bool conv = false, fell = !FULL && !start_ok;
+    int it = 0;
+    if (!fell) {
+        for (; it < (FULL ? MirrorCfg<A>::maxit : 1); ++it) {
+            A F = -a * S, Fp = -S;
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                const A y = a * xof(i);
+                const A l = log1p_(y);
+                F = fma_(A(gval<D, T, SH>(i, p)), phi_(y, l), F);
+                Fp = fma_(A(d[i]), l, Fp);
+            }
+            if (F > A(0)) hi = a; else lo = a;
+            A an = a - F * rcp_(Fp);
+            // a step onto the bracket's end is the root itself (F = 0)
+            if (FULL && !(an >= lo && an <= hi)) an = A(0.5) * (lo + hi);
+            conv = F == A(0) || abs_(an - a) <= A(MirrorCfg<A>::tol) * an;
+            a = an;
+            if (conv) { ++it; break; }
+        }
+        // No root: dH < 0 on the whole of (1, a*), so no iterate sees
+        // dH > 0 and the bisections close the bracket on a*.  A root is
+        // certain once some iterate had dH > 0, or when the iteration
+        // converged away from the edge (near the gate dH is of the order of
+        // its rounding, and Newton may converge on the root from the left).
+        if (FULL) fell = !(hi < astar) && !(conv && astar - a > A(4 * MirrorCfg<A>::tol) * a);
+        else fell = !(a > A(1) && a < astar);
+    }
+    info.iters = it;
+    info.fallback = fell;
+    return fell ? aL : a;
+}
+
 // Path length of one cell from the populations (p) and d = feq - g.  The
 // gate and the series run in T; the exact path, with its guard, in A (a
 // cell whose x reach beyond the series bound has populations far from the
 // equilibrium, and the update multiplies an error of alpha by x relative to
 // g: double sums there keep that product below the storage rounding).
 template <int D, typename T, typename A, int MODE, bool SH>
-__device__ inline T path_length(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], double beta64, CellInfo &info)
+__device__ __attribute__((always_inline)) inline T path_length(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], double beta64, CellInfo &info)
 {
     constexpr int Q = Lat<D>::Q;
     const T beta = T(beta64);
@@ -494,7 +597,11 @@ __device__ inline T path_length(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q]
     info.gated = 0;
     info.guarded = 0;
     info.exact = 0;
+    info.iters = 0;
+    info.fallback = 0;
     if (MODE == MODE_BGK) return T(2);
+    // the mirror modes start from alpha_Lower
+    constexpr int CMODE = is_mirror_mode(MODE) ? MODE_LOWER : MODE;
 
     // one pass: x, x_min, max|x| and the power moments
     // Tm[k] = <g, x^k> = sum d x^(k-1) (k = 2..K) and Nm[k] = <g, x^k>_-
@@ -546,8 +653,9 @@ __device__ inline T path_length(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q]
             C += T(ck[k - 2]) * Tm[k];
         }
         const T aL = conj_root(T(0.5) * Nm[3], b1, C1);
-        if (MODE == MODE_LOWER) {
+        if (CMODE == MODE_LOWER) {
             alpha = aL;
+            if (is_mirror_mode(MODE)) alpha = mirror_alpha<D, T, T, SH, MODE == MODE_ELBM>(p, d, aL, xmin, info);
         } else {
             // Bp = sum_m r_m aL^m P_{3+m}, P_k = Tm[k] - Nm[k], by Horner
             T Bp = T(rk[K - 3]) * (Tm[K] - Nm[K]);
@@ -559,7 +667,8 @@ __device__ inline T path_length(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q]
         info.exact = 1;
         // alpha and its positivity guard (App. D) in A
         A xm;
-        A al = alpha_exact<D, T, A, MODE, SH>(p, d, A(beta64), xm);
+        A al = alpha_exact<D, T, A, CMODE, SH>(p, d, A(beta64), xm);
+        if (is_mirror_mode(MODE)) al = mirror_alpha<D, T, A, SH, MODE == MODE_ELBM>(p, d, al, xm, info);
         if (xm < A(0)) {
             const A amax = A(-1) * rcp_(A(beta64) * xm);
             if (al > amax) {

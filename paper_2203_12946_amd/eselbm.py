@@ -16,11 +16,12 @@ _LIB_PATH = pathlib.Path(__file__).resolve().parent / "libeselbm.so"
 
 D2Q9, D3Q27 = 0, 1
 F64, F32, F16_SHIFTED, F32_SHIFTED = 0, 1, 2, 3
-MODE_HIGHER, MODE_BGK, MODE_LOWER = 0, 1, 2
+MODE_HIGHER, MODE_BGK, MODE_LOWER, MODE_ELBM, MODE_ITERATE1 = 0, 1, 2, 3, 4
 OK, E_ARG, E_UNSUPPORTED, E_HIP, E_NONPOSITIVE = 0, 1, 2, 3, 4
 
 DTYPES = {"f64": F64, "f32": F32, "f16s": F16_SHIFTED, "f32s": F32_SHIFTED}
-MODES = {"higher": MODE_HIGHER, "bgk": MODE_BGK, "lower": MODE_LOWER}
+MODES = {"higher": MODE_HIGHER, "bgk": MODE_BGK, "lower": MODE_LOWER, "elbm": MODE_ELBM,
+         "iterate1": MODE_ITERATE1}
 LATTICES = {"D2Q9": D2Q9, "D3Q27": D3Q27}
 TORCH_STORAGE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float16,
                  F32_SHIFTED: torch.float32}
@@ -41,6 +42,7 @@ class Stats(ctypes.Structure):
         ("alpha_mean", ctypes.c_double), ("n_cells", ctypes.c_longlong), ("n_gated", ctypes.c_longlong),
         ("n_guard", ctypes.c_longlong), ("n_nonpos", ctypes.c_longlong),
         ("n_alpha_lt2", ctypes.c_longlong), ("n_exact", ctypes.c_longlong),
+        ("n_newton", ctypes.c_longlong), ("n_mirror_fallback", ctypes.c_longlong),
     ]
 
     def as_dict(self) -> dict:
@@ -56,6 +58,7 @@ _SIGNATURES = {
     "eselbm_set_mode": [_vp, ctypes.c_int],
     "eselbm_set_stats": [_vp, ctypes.c_int],
     "eselbm_set_alpha_field": [_vp, _vp],
+    "eselbm_set_nut_field": [_vp, _vp],
     "eselbm_set_force": [_vp, _vp],
     "eselbm_init_equilibrium": [_vp, _vp, _vp, _vp, _vp],
     "eselbm_step": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp],
@@ -140,6 +143,7 @@ class Solver:
         with torch.cuda.device(self.device):
             _check(lib.eselbm_create(ctypes.byref(self._h), LATTICES[lattice], nx, ny, nz, self.dtype_code))
         self._alpha = None
+        self._nut = None
         self._force = None
         self.set_mode(mode)
 
@@ -161,6 +165,11 @@ class Solver:
         """Register a [*shape] compute-dtype tensor receiving per-cell alpha."""
         self._alpha = alpha
         _check(lib.eselbm_set_alpha_field(self._h, _dev(alpha, self.compute_dtype, self.cells)))
+
+    def set_nut_field(self, nut: torch.Tensor | None):
+        """Register a [*shape] compute-dtype tensor receiving per-cell nu_T (Eq. nuT)."""
+        self._nut = nut
+        _check(lib.eselbm_set_nut_field(self._h, _dev(nut, self.compute_dtype, self.cells)))
 
     def set_force(self, F: torch.Tensor | None):
         """Register a [D, *shape] float32 body-force density (F32 storage only)."""

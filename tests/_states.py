@@ -55,3 +55,24 @@ def three_regime_state(D, shape, seed):
     amp = rng.choice([2e-4, 1.5e-3, 3e-2], size=tuple(shape))
     g = g * (1 + amp * rng.uniform(-1, 1, g.shape))
     return unstream(g)
+
+
+def mixed_mirror_lattice(D, shape, seed, sigma=1.2, amps=(2e-4, 4e-3, 1.2e-2, 0.05)):
+    """Pulled cells in five kinds, about a fifth each: relative perturbations
+    of an equilibrium (random rho, u) of uniform amplitude 2e-4 (gated),
+    4e-3 and 1.2e-2 (max|x| from 1.4e-3 to 2.5e-2: the power-series range of
+    the path-length sums), 0.05 (their exact range), and log-normal
+    populations far from equilibrium (often without a mirror root);
+    un-streamed so that one step collides exactly these cells."""
+    rng = np.random.default_rng(seed)
+    u = 0.03 * rng.standard_normal((D,) + tuple(shape))
+    rho = 1 + 0.01 * rng.standard_normal(tuple(shape))
+    g = oracle.init_equilibrium(rho, u)
+    kind = rng.integers(0, len(amps) + 1, size=tuple(shape))
+    pert = np.zeros(g.shape)
+    for k, a in enumerate(amps):
+        pert = np.where(kind == k, a * rng.uniform(-1, 1, g.shape), pert)
+    g = g * (1 + pert)
+    far = np.exp(rng.normal(0, sigma, g.shape))
+    g = np.where(kind == len(amps), g * far, g)
+    return unstream(g)

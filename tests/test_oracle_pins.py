@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
-from tests._states import null_space_direction, perturbed_state
+from tests._states import mixed_mirror_lattice, null_space_direction, perturbed_state
 
 THETA0 = 1.0 / 3.0
 
@@ -560,24 +560,6 @@ def test_light_cone_block_reproduces_full_grid():
 # --------------------------------------------------------------------------
 # Iterative ELBM modes of the whole step (Sec. III mirror condition, Sec. V C)
 # --------------------------------------------------------------------------
-def _mixed_lattice(D, shape, seed, sigma=1.2):
-    """Pulled cells near equilibrium (gated), moderately off it, and far off
-    it (log-normal populations, often without a mirror root), un-streamed so
-    that one step collides exactly these cells."""
-    from tests._states import unstream
-    rng = np.random.default_rng(seed)
-    u = 0.03 * rng.standard_normal((D,) + shape)
-    rho = 1 + 0.01 * rng.standard_normal(shape)
-    g = oracle.init_equilibrium(rho, u)
-    kind = rng.integers(0, 3, size=shape)
-    pert = np.where(kind == 0, 2e-4 * rng.uniform(-1, 1, g.shape),
-                    np.where(kind == 1, 0.05 * rng.uniform(-1, 1, g.shape), 0.0))
-    g = g * (1 + pert)
-    far = np.exp(rng.normal(0, sigma, g.shape))
-    g = np.where(kind == 2, g * far, g)
-    return unstream(g)
-
-
 @pytest.mark.parametrize("mode", ["elbm", "iterate1"])
 @pytest.mark.parametrize("D,shape", [(2, (12, 14)), (3, (4, 5, 6))])
 def test_mirror_modes_whole_step(D, shape, mode):
@@ -590,7 +572,7 @@ def test_mirror_modes_whole_step(D, shape, mode):
     change of the step is <= 0 (Sec. III: the mirror is isentropic and
     beta < 1 adds dissipation; Sec. IV A: alpha_Lower never produces
     entropy)."""
-    f = _mixed_lattice(D, shape, 40 + D)
+    f = mixed_mirror_lattice(D, shape, 40 + D)
     tau = 2e-3
     beta = 1 / (2 * tau + 1)
     out, alpha, (ng, nd, nn) = oracle.step(f, 1, tau, mode=mode, want_alpha=True)
