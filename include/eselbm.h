@@ -197,14 +197,19 @@ eselbm_status eselbm_moments(eselbm_handle h, const void *f, double *rho, double
  * differentiated through x_min).
  *   f_n:      state at step n (storage type), the input of the step.
  *   lam_next: adjoint of the state at step n+1 (compute type, Q * cells).
+ *   seed_next: NULL, or a per-cell loss seed of the state at step n+1
+ *             (compute type, [1 + D][cells], as eselbm_dissipation_seed
+ *             writes it): the step uses lam_next_i + s0 + c_i . s in place
+ *             of lam_next_i, without writing lam_next.
  *   lam_n:    receives the adjoint of the state at step n (compute type).
- *             Must not alias lam_next.
+ *             Must not alias lam_next or seed_next.
  *   force_grad: NULL, or with a force registered, a device float
  *             [D][cells] buffer to which dL/dF of this step is ADDED.
  * Supported for ESELBM_F32, ESELBM_F32_SHIFTED and ESELBM_F64 in modes
  * HIGHER, LOWER and BGK (ESELBM_E_UNSUPPORTED otherwise). */
 eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next,
-                                  void *lam_n, double tau, void *force_grad, void *stream);
+                                  const void *seed_next, void *lam_n, double tau, void *force_grad,
+                                  void *stream);
 
 /* Kinetic-energy loss and its seed (not in the paper):
  * L = sum_x rho |u|^2 / 2 of state f.  The value is ADDED to *loss_dev (a
@@ -229,6 +234,16 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
  * overlap on different streams race. */
 eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
                                       double weight, void *force_grad, void *stream);
+
+/* The seed of the same dissipation loss in compact form (not in the paper):
+ * L depends on f only through rho and u, so dL/df_i = s0 + c_i . s per cell.
+ * seed (compute type, [1 + D][cells]) is overwritten with (s0, s); passed
+ * to eselbm_adjoint_step as seed_next it adds dL/df to the adjoint as that
+ * step reads it, instead of a pass over all Q adjoint values.  With a force
+ * registered, the direct part of dL/dF is ADDED to force_grad as in
+ * eselbm_dissipation_loss.  Scratch: as for eselbm_dissipation_loss. */
+eselbm_status eselbm_dissipation_seed(eselbm_handle h, const void *f, void *seed, double weight,
+                                      void *force_grad, void *stream);
 
 /* Adjoint of eselbm_init_equilibrium with respect to u (rho held fixed):
  * grad_u[a][x] = sum_i lam[i][x] d feq_i(rho, u)/d u_a.

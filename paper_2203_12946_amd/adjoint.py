@@ -8,9 +8,10 @@ schedules them:
   weight * sum_x |omega|^2 after every step.
 * ``Rollout.backward`` sweeps the checkpoint segments in reverse.  For each
   segment it recomputes the segment's states from its checkpoint, then applies
-  the adjoint step kernel from the last state down to the first, adding the
-  per-step loss seeds on the way.  The adjoint kernel also accumulates the
-  body-force gradient.
+  the adjoint step kernel from the last state down to the first.  The
+  per-step loss seeds travel in compact per-cell form (dL/df_i = s0 + c_i.s)
+  and each is added by the adjoint step that reads it.  The adjoint kernel
+  also accumulates the body-force gradient.
 
 Autograd functions wrap the three pieces of a training objective:
 ``equilibrium`` (initial state from rho, u; gradient w.r.t. u), ``rollout``
@@ -64,9 +65,14 @@ class Rollout:
             lam.copy_(lam_final)
         other = s.empty_adjoint()
         w = None if self.diss_weight is None else self.diss_weight * float(diss_grad)
+        # The loss seed of state f^n is kept in compact per-cell form and
+        # added by the adjoint step that reads lambda^n (the next one down).
+        seed = s.empty_seed() if w else None
+        pending = None
         n_end = self.nsteps
         if w:
-            s.dissipation_loss(self._state_at_end(), lam=lam, weight=w, force_grad=force_grad)
+            s.dissipation_seed(self._state_at_end(), seed, weight=w, force_grad=force_grad)
+            pending = seed
         seg_starts = sorted(self.ckpts)
         for start in reversed(seg_starts):
             stop = min(start + self.K, n_end)
@@ -78,10 +84,12 @@ class Rollout:
                 states.append(nxt)
             for n in range(stop - 1, start - 1, -1):
                 f_n = states[n - start]
-                s.adjoint_step(f_n, lam, other, self.tau, force_grad=force_grad)
+                s.adjoint_step(f_n, lam, other, self.tau, force_grad=force_grad, seed_next=pending)
                 lam, other = other, lam
+                pending = None
                 if w and n >= 1:
-                    s.dissipation_loss(f_n, lam=lam, weight=w, force_grad=force_grad)
+                    s.dissipation_seed(f_n, seed, weight=w, force_grad=force_grad)
+                    pending = seed
             n_end = start
         return lam
 

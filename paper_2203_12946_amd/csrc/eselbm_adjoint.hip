@@ -197,7 +197,27 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
         asm volatile("" : "+s"(o));
         return o;
     };
-    auto lam_at = [&](int i) { return *lane_ptr(lin + opaque((long long)i * N + row0), (unsigned)x); };
+    // lambda_i of the state after the step, plus the optional loss seed of
+    // that state, s0 + c_i . s (affine in the velocity: the seeds of losses
+    // that depend on f through rho and u only)
+    T sd[4] = {T(0), T(0), T(0), T(0)};
+    const T *seed = (const T *)a.seed;
+    if (seed) {
+#pragma unroll
+        for (int c = 0; c <= D; ++c) sd[c] = seed[(long long)c * N + row0 + x];
+    }
+    auto lam_at = [&](int i) {
+        T v = *lane_ptr(lin + opaque((long long)i * N + row0), (unsigned)x);
+        if (seed) {
+            v += sd[0];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                if (Lat<D>::c(i, c) > 0) v += sd[1 + c];
+                if (Lat<D>::c(i, c) < 0) v -= sd[1 + c];
+            }
+        }
+        return v;
+    };
     // adjoint of the pull: lam_n_i(x - c_i) = mu_i(x)
     auto push = [&](int i, T m) {
         const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
@@ -845,7 +865,7 @@ __global__ __launch_bounds__(256) void k_vorticity(Grid g, const float *__restri
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restrict__ u, const float *__restrict__ rho,
-                                                   const float *__restrict__ vort, T *lam, double weight,
+                                                   const float *__restrict__ vort, T *lam, T *seed, double weight,
                                                    float *force_grad)
 {
     constexpr int Q = Lat<D>::Q;
@@ -867,7 +887,16 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restri
     double uc[3] = {0, 0, 0};
 #pragma unroll
     for (int c = 0; c < D; ++c) uc[c] = (double)u[c * N + cell];
-    // du_c/df_i = (c_ic - u_c) / rho
+    // du_c/df_i = (c_ic - u_c) / rho: dL/df_i = s0 + c_i . s with
+    // s0 = -ubar . u / rho and s = ubar / rho
+    if (seed) {
+        double ubu = 0.0;
+#pragma unroll
+        for (int c = 0; c < D; ++c) ubu += ub[c] * uc[c];
+        seed[cell] = (T)(-ubu * ir);
+#pragma unroll
+        for (int c = 0; c < D; ++c) seed[(long long)(1 + c) * N + cell] = (T)(ub[c] * ir);
+    }
     if (lam) {
         double ubu = 0.0;
 #pragma unroll
@@ -892,7 +921,7 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restri
 
 template <int D>
 static hipError_t launch_diss_d(int dtype, const Grid &g, const void *f, const float *force, double *loss, void *lam,
-                                double weight, float *force_grad, hipStream_t s)
+                                void *seed, double weight, float *force_grad, hipStream_t s)
 {
     hipError_t e = ensure_scratch(g);
     if (e != hipSuccess) return e;
@@ -916,22 +945,22 @@ static hipError_t launch_diss_d(int dtype, const Grid &g, const void *f, const f
     hipLaunchKernelGGL((k_vorticity<D>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.vort, part, weight);
     if (loss)
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (const double *)part, stencil_blocks(g), loss);
-    if (lam || force_grad) {
+    if (lam || seed || force_grad) {
         if (dtype == 0)
             hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.rho,
-                               g_scratch.vort, (double *)lam, weight, force_grad);
+                               g_scratch.vort, (double *)lam, (double *)seed, weight, force_grad);
         else
             hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.rho,
-                               g_scratch.vort, (float *)lam, weight, force_grad);
+                               g_scratch.vort, (float *)lam, (float *)seed, weight, force_grad);
     }
     return hipGetLastError();
 }
 
 hipError_t launch_dissipation_loss(int dtype, const Grid &g, const void *f, const float *force, double *loss,
-                                   void *lam, double weight, float *force_grad, hipStream_t s)
+                                   void *lam, void *seed, double weight, float *force_grad, hipStream_t s)
 {
-    return g.D == 2 ? launch_diss_d<2>(dtype, g, f, force, loss, lam, weight, force_grad, s)
-                    : launch_diss_d<3>(dtype, g, f, force, loss, lam, weight, force_grad, s);
+    return g.D == 2 ? launch_diss_d<2>(dtype, g, f, force, loss, lam, seed, weight, force_grad, s)
+                    : launch_diss_d<3>(dtype, g, f, force, loss, lam, seed, weight, force_grad, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -234,11 +234,12 @@ eselbm_status eselbm_moments(eselbm_handle h, const void *f, double *rho, double
     return ESELBM_OK;
 }
 
-eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next, void *lam_n, double tau,
-                                  void *force_grad, void *stream)
+eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next, const void *seed_next,
+                                  void *lam_n, double tau, void *force_grad, void *stream)
 {
     if (!h || !f_n || !lam_next || !lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: NULL argument");
     if (lam_next == lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: lam_n must not alias lam_next");
+    if (seed_next && seed_next == lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: lam_n must not alias seed_next");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: tau must be finite and > 0");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: F16 storage has no adjoint");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: force_grad without a registered force");
@@ -252,6 +253,7 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
     a.beta = 1.0 / (2.0 * tau + 1.0);
     a.force = h->force;
     a.force_grad = (float *)force_grad;
+    a.seed = seed_next;
     hipError_t e = launch_adjoint(h->dtype, h->mode, a, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_adjoint_step: launch");
     return ESELBM_OK;
@@ -273,9 +275,21 @@ eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *lo
     if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: NULL argument");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: force_grad without a registered force");
-    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, loss_dev, lam, weight, (float *)force_grad,
-                                           (hipStream_t)stream);
+    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, loss_dev, lam, nullptr, weight,
+                                           (float *)force_grad, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_loss: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_dissipation_seed(eselbm_handle h, const void *f, void *seed, double weight, void *force_grad,
+                                      void *stream)
+{
+    if (!h || !f || !seed) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: NULL argument");
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: F16 storage");
+    if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: force_grad without a registered force");
+    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, nullptr, nullptr, seed, weight,
+                                           (float *)force_grad, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_seed: launch");
     return ESELBM_OK;
 }
 

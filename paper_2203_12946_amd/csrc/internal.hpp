@@ -52,12 +52,14 @@ struct AdjArgs {
     double beta;
     const float *force;
     float *force_grad;
+    const void *seed;  // compute type [1 + D][N] or null: lam_next_i += s0 + c_i . s
 };
 hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s);
 hipError_t launch_kinetic_loss(int dtype, const Grid &g, const void *f, double *loss, void *lam,
                                double scale, hipStream_t s);
 hipError_t launch_dissipation_loss(int dtype, const Grid &g, const void *f, const float *force,
-                                   double *loss, void *lam, double weight, float *force_grad, hipStream_t s);
+                                   double *loss, void *lam, void *seed, double weight, float *force_grad,
+                                   hipStream_t s);
 hipError_t launch_equilibrium_vjp(int dtype, const Grid &g, const double *rho, const double *u,
                                   const void *lam, double *grad_u, hipStream_t s);
 

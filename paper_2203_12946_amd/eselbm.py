@@ -64,9 +64,10 @@ _SIGNATURES = {
     "eselbm_step": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp],
     "eselbm_alpha_stats": [_vp, ctypes.POINTER(Stats), ctypes.c_int, _vp],
     "eselbm_moments": [_vp, _vp, _vp, _vp, _vp],
-    "eselbm_adjoint_step": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "eselbm_adjoint_step": [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_kinetic_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
     "eselbm_dissipation_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "eselbm_dissipation_seed": [_vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_equilibrium_vjp": [_vp, _vp, _vp, _vp, _vp, _vp],
 }
 EXPORTS = tuple(_SIGNATURES) + ("eselbm_last_error",)
@@ -213,10 +214,15 @@ class Solver:
         return rho, u
 
     # ---- adjoint ----------------------------------------------------------
-    def adjoint_step(self, f_n, lam_next, lam_n, tau: float, force_grad=None, stream=None):
+    def empty_seed(self) -> torch.Tensor:
+        """[1 + D, *shape] compute-dtype buffer for a compact loss seed."""
+        return torch.empty((1 + self.D,) + self.shape, dtype=self.compute_dtype, device=self.device)
+
+    def adjoint_step(self, f_n, lam_next, lam_n, tau: float, force_grad=None, seed_next=None, stream=None):
         n = self.Q * self.cells
         _check(lib.eselbm_adjoint_step(
             self._h, _dev(f_n, self.storage_dtype, n), _dev(lam_next, self.compute_dtype, n),
+            _dev(seed_next, self.compute_dtype, (1 + self.D) * self.cells) if seed_next is not None else _vp(None),
             _dev(lam_n, self.compute_dtype, n), float(tau),
             _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
             _stream(stream)))
@@ -234,6 +240,13 @@ class Solver:
             _dev(loss, torch.float64, 1) if loss is not None else _vp(None),
             _dev(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
             float(weight),
+            _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+            _stream(stream)))
+
+    def dissipation_seed(self, f, seed, weight: float = 1.0, force_grad=None, stream=None):
+        _check(lib.eselbm_dissipation_seed(
+            self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
+            _dev(seed, self.compute_dtype, (1 + self.D) * self.cells), float(weight),
             _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
             _stream(stream)))
 

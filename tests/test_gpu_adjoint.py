@@ -287,3 +287,41 @@ def test_dot_product_identity(es):
     rhs = float(np.sum(lam * jv))
     _log(f"[dot] lhs={lhs:.12e} rhs={rhs:.12e}")
     assert abs(lhs - rhs) <= 1e-7 * abs(rhs)
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_compact_seed_matches_full_seed(es, dtype):
+    """The compact dissipation seed (s0, s) expands to the Q-population seed
+    that eselbm_dissipation_loss adds (dL/df_i = s0 + c_i . s), and an adjoint
+    step given the compact seed equals one given lambda plus that seed."""
+    shape = (6, 7, 9)
+    f0 = _state(3, shape, 9, 1e-3)
+    tau = 2e-3
+    s = es.Solver("D3Q27", shape, dtype=dtype)
+    fd = _t(f0).to(s.storage_dtype).cuda()
+    if dtype == "f32":
+        s.set_force(_t(W.random_force(shape, 3, amplitude=1e-3, seed=5)).float().cuda())
+    full = torch.zeros((27,) + shape, dtype=s.compute_dtype, device="cuda")
+    fg_full = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda") if dtype == "f32" else None
+    s.dissipation_loss(fd, lam=full, weight=0.7, force_grad=fg_full)
+    seed = s.empty_seed()
+    fg_c = torch.zeros_like(fg_full) if fg_full is not None else None
+    s.dissipation_seed(fd, seed, weight=0.7, force_grad=fg_c)
+    c, _ = oracle.lattice(3)
+    sd = seed.double().cpu().numpy()
+    expanded = sd[0][None] + np.tensordot(c.astype(float), sd[1:], axes=(1, 0))
+    tol = 1e-14 if dtype == "f64" else 2e-6
+    scale = np.max(np.abs(expanded))
+    assert np.max(np.abs(expanded - full.double().cpu().numpy())) <= tol * scale
+    if fg_full is not None:
+        assert torch.equal(fg_full, fg_c)
+    lam = torch.from_numpy(np.random.default_rng(10).standard_normal(f0.shape)).to(s.compute_dtype).cuda()
+    a = s.empty_adjoint()
+    b = s.empty_adjoint()
+    s.adjoint_step(fd, lam, a, tau, seed_next=seed)
+    s.adjoint_step(fd, lam + full, b, tau)
+    torch.cuda.synchronize()
+    err = float((a.double() - b.double()).abs().max() / b.double().abs().max())
+    _log(f"[compact seed {dtype}] expand err {np.max(np.abs(expanded - full.double().cpu().numpy())) / scale:.2e}, "
+         f"seeded-step err {err:.2e}")
+    assert err <= (1e-13 if dtype == "f64" else 1e-6)
