@@ -70,6 +70,9 @@ def _load():
     lib.orc_step.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
                              ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, dp, llp]
     lib.orc_step.restype = ctypes.c_int
+    lib.orc_step_walls.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
+                                   dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, llp]
+    lib.orc_step_walls.restype = ctypes.c_int
     lib.orc_init_equilibrium.argtypes = [ctypes.c_int, ctypes.c_longlong, dp, dp, dp]
     lib.orc_init_equilibrium.restype = None
     lib.orc_moments.argtypes = [ctypes.c_int, ctypes.c_longlong, dp, dp, dp]
@@ -207,6 +210,37 @@ def step(f, nsteps: int, tau: float, mode: str = "higher", force=None,
     rc = lib.orc_step(D, nx, ny, nz, _dp(f), _dp(out), int(nsteps), float(tau), MODES[mode],
                       _dp(F), _dp(alpha),
                       counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+    if rc == -1:
+        raise OracleError("non-positive or non-finite pre-collision population")
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    if want_alpha:
+        return out, alpha, (int(counts[0]), int(counts[1]), int(counts[2]))
+    return out
+
+
+def step_walls(f, nsteps: int, tau: float, walls, wall_velocity=None, mode: str = "higher",
+               want_alpha: bool = False):
+    """Steps with diffuse walls (the boundary rule of the cavity, Sec. V C).
+
+    ``walls``: per axis (x, y[, z]) True for walls at -1/2 and n - 1/2, False
+    for periodic.  ``wall_velocity``: {(axis, side): velocity} with side 0
+    the low and 1 the high wall (default: every wall at rest).  With
+    ``want_alpha`` returns ``(state, alpha, (n_gated, n_guarded, n_fallback))``.
+    """
+    lib = _load()
+    f = _f64(f)
+    D, nx, ny, nz = _grid(f)
+    mask = sum(1 << a for a, on in enumerate(walls) if on)
+    uw = np.zeros((3, 2, 3))
+    for (a, sd), v in (wall_velocity or {}).items():
+        uw[a, sd, :len(v)] = v
+    uw = _f64(uw)
+    out = np.empty_like(f)
+    alpha = np.empty(f.shape[1:]) if want_alpha else None
+    counts = np.zeros(3, dtype=np.int64)
+    rc = lib.orc_step_walls(D, nx, ny, nz, mask, _dp(uw), _dp(f), _dp(out), int(nsteps), float(tau),
+                            MODES[mode], _dp(alpha), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
     if rc == -1:
         raise OracleError("non-positive or non-finite pre-collision population")
     if rc != 0:

@@ -432,6 +432,112 @@ int orc_step(int D, int nx, int ny, int nz, const double *f_in, double *f_out, i
     return bad ? -1 : 0;
 }
 
+/* ---------------------------------------------------------------------
+ * Whole-lattice steps with walls.
+ *
+ * The lid-driven cavity of Sec. V C uses the diffuse boundary condition of
+ * Ansumali and Karlin (2002), which the paper cites without restating.  It
+ * is written here from that rule:
+ *   walls: bit a set -> axis a is bounded by walls at -1/2 and n_a - 1/2,
+ *          half-way between nodes; otherwise the axis is periodic.
+ *   uw:    [axis][side][3] wall velocities, side 0 the low wall, 1 the high.
+ * For a node x and a population i with source s = x - c_i:
+ *   - if s lies inside on every walled axis, g_i = f*_i(s) (periodic axes
+ *     wrap);
+ *   - otherwise i is re-emitted by the wall of the first walled axis on
+ *     which s lies outside (axis order x, y, z): g_i = rho_w feq_i(1, uw),
+ *     with one rho_w per node such that the re-emitted populations carry
+ *     exactly the mass that left the node into the walls:
+ *       rho_w = sum_{j: x + c_j outside} f*_j(x) / sum_{i re-emitted} feq_i(1, uw(i)).
+ * Then the collision as in orc_step.  No forcing.
+ * ------------------------------------------------------------------- */
+int orc_step_walls(int D, int nx, int ny, int nz, int walls, const double *uw, const double *f_in,
+                   double *f_out, int nsteps, double tau, int mode, double *alpha_out, long long *counts)
+{
+    int c[ORC_QMAX * 3];
+    double w[ORC_QMAX];
+    int Q = orc_lattice(D, c, w);
+    long long N = (long long)nx * ny * nz;
+    const int n[3] = {nx, ny, nz};
+    double beta = 1.0 / (2.0 * tau + 1.0);
+    /* feq_i(1, uw) of every wall */
+    double weq[3][2][ORC_QMAX];
+    for (int a = 0; a < D; ++a)
+        for (int sd = 0; sd < 2; ++sd) orc_equilibrium(D, 1.0, uw + 3 * (2 * a + sd), weq[a][sd]);
+    double *cur = (double *)malloc(sizeof(double) * Q * N);
+    double *nxt = (double *)malloc(sizeof(double) * Q * N);
+    if (!cur || !nxt) { free(cur); free(nxt); return -2; }
+    memcpy(cur, f_in, sizeof(double) * Q * N);
+    int bad = 0;
+    long long ngated = 0, nguard = 0, nnoroot = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        int last = (s == nsteps - 1);
+        long long sg = 0, sd = 0, sn = 0;
+#pragma omp parallel for collapse(2) reduction(+ : sg, sd, sn) reduction(| : bad)
+        for (int z = 0; z < nz; ++z) {
+            for (int y = 0; y < ny; ++y) {
+                for (int xx = 0; xx < nx; ++xx) {
+                    const int xc[3] = {xx, y, z};
+                    long long cell = ((long long)z * ny + y) * nx + xx;
+                    double g[ORC_QMAX], feq[ORC_QMAX], det[16];
+                    int wall_of[ORC_QMAX]; /* -1, or 2 * axis + side of the emitting wall */
+                    double out_mass = 0.0, in_eq = 0.0;
+                    for (int i = 0; i < Q; ++i) {
+                        int src[3], dst_out = 0;
+                        wall_of[i] = -1;
+                        for (int a = 0; a < 3; ++a) {
+                            src[a] = xc[a] - c[3 * i + a];
+                            if (a < D && (walls >> a & 1)) {
+                                if (wall_of[i] < 0 && (src[a] < 0 || src[a] >= n[a]))
+                                    wall_of[i] = 2 * a + (src[a] < 0 ? 0 : 1);
+                                int d = xc[a] + c[3 * i + a];
+                                if (d < 0 || d >= n[a]) dst_out = 1;
+                            } else {
+                                src[a] = (int)wrap(src[a], n[a]);
+                            }
+                        }
+                        if (dst_out) out_mass += cur[(long long)i * N + cell];
+                        if (wall_of[i] < 0) {
+                            g[i] = cur[(long long)i * N + ((long long)src[2] * ny + src[1]) * nx + src[0]];
+                        } else {
+                            in_eq += weq[wall_of[i] / 2][wall_of[i] % 2][i];
+                        }
+                    }
+                    if (in_eq > 0.0) {
+                        double rho_w = out_mass / in_eq;
+                        for (int i = 0; i < Q; ++i)
+                            if (wall_of[i] >= 0) g[i] = rho_w * weq[wall_of[i] / 2][wall_of[i] % 2][i];
+                    }
+                    double rho, u[3] = {0.0, 0.0, 0.0};
+                    orc_cell_moments(D, g, &rho, u);
+                    orc_equilibrium(D, rho, u, feq);
+                    if (orc_path_length(Q, g, feq, beta, mode, det) != 0) {
+                        bad |= 1;
+                        continue;
+                    }
+                    double alpha = det[0];
+                    for (int i = 0; i < Q; ++i)
+                        nxt[(long long)i * N + cell] = g[i] + alpha * beta * (feq[i] - g[i]);
+                    if (last) {
+                        if (alpha_out) alpha_out[cell] = alpha;
+                        sg += det[12] > 0.0;
+                        sd += det[13] > 0.0;
+                        sn += det[15] > 0.0;
+                    }
+                }
+            }
+        }
+        if (bad) break;
+        if (last) { ngated = sg; nguard = sd; nnoroot = sn; }
+        double *t = cur; cur = nxt; nxt = t;
+    }
+    if (!bad) memcpy(f_out, cur, sizeof(double) * Q * N);
+    free(cur);
+    free(nxt);
+    if (counts) { counts[0] = ngated; counts[1] = nguard; counts[2] = nnoroot; }
+    return bad ? -1 : 0;
+}
+
 /* Equilibrium state f = feq(rho, u) for every cell; rho [N], u [D][N]. */
 void orc_init_equilibrium(int D, long long N, const double *rho, const double *u, double *f)
 {

@@ -613,3 +613,50 @@ def test_mirror_modes_whole_step(D, shape, mode):
         m_in = np.tensordot(wts, f, axes=(0, 0)).sum()
         m_out = np.tensordot(wts, out, axes=(0, 0)).sum()
         assert abs(m_in - m_out) < 1e-12 * np.abs(f).sum()
+
+
+# --------------------------------------------------------------------------
+# Diffuse walls (the cavity's boundary rule, Sec. V C)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("D,shape", [(2, (6, 7)), (3, (4, 5, 6))])
+def test_walls_rest_state_is_fixed(D, shape):
+    """Fluid at rest in a closed box of resting walls stays f = w: every wall
+    node sends w_j into the walls and gets w_i back."""
+    _, w = oracle.lattice(D)
+    f = np.broadcast_to(w.reshape((-1,) + (1,) * D), (len(w),) + shape).copy()
+    out = oracle.step_walls(f, 5, 0.01, walls=[True] * D)
+    assert np.max(np.abs(out - f)) < 1e-15
+
+
+def test_walls_cavity_conserves_mass_and_mirrors():
+    """The diffuse walls return to the fluid exactly the mass that left it,
+    and the cavity with the lid moving the other way is the mirror image."""
+    n = 12
+    f = oracle.init_equilibrium(np.ones((n, n)), np.zeros((2, n, n)))
+    a = oracle.step_walls(f, 200, 1e-3, walls=[True, True], wall_velocity={(1, 1): (0.1, 0.0)})
+    b = oracle.step_walls(f, 200, 1e-3, walls=[True, True], wall_velocity={(1, 1): (-0.1, 0.0)})
+    assert abs(a.sum() - f.sum()) < 1e-13 * f.sum()
+    assert np.all(a > 0)
+    # mirror x -> n-1-x maps population (cx, cy) to (-cx, cy)
+    c, _ = oracle.lattice(2)
+    perm = [int(np.flatnonzero((c[:, 0] == -c[i, 0]) & (c[:, 1] == c[i, 1]))[0]) for i in range(9)]
+    assert np.max(np.abs(b - a[perm][:, :, ::-1])) < 1e-13
+
+
+@pytest.mark.parametrize("tau", [0.1, 0.3])
+def test_walls_couette_profile(tau):
+    """Plane Couette flow between diffuse walls (x periodic, top wall moving at
+    U).  In steady state the populations with c_y = +1 carry x-momentum
+    rho u_x / 6 at equilibrium (product form with u_y = 0), the wall re-emits
+    them with none, and relaxation at 2 beta then gives the exact linear
+    profile u(y) = U (y + 1/2 + tau) / (ny + 2 tau): a slip of tau du/dy at
+    each wall."""
+    ny, nx, U = 16, 4, 0.05
+    f = oracle.init_equilibrium(np.ones((ny, nx)), np.zeros((2, ny, nx)))
+    out = oracle.step_walls(f, 40000, tau, walls=[False, True], wall_velocity={(1, 1): (U, 0.0)}, mode="bgk")
+    r, v = oracle.moments(out)
+    y = np.arange(ny)
+    exact = U * (y + 0.5 + tau) / (ny + 2 * tau)
+    assert np.max(np.abs(v[0] - exact[:, None])) < 1e-12
+    assert np.max(np.abs(v[1])) < 1e-11
+    assert np.max(np.abs(r - 1)) < 1e-11
