@@ -31,7 +31,8 @@ sys.path.insert(0, str(ROOT))
 
 HBM_PEAK_GBS = 8000.0
 METRIC = "ESELBM MLUPS & % HBM roofline (D3Q27 FP32 vs FP64); adjoint/forward time"
-KERNEL_SOURCES = ["paper_2203_12946_amd/csrc/eselbm_step.hip", "paper_2203_12946_amd/csrc/lattice.hpp"]
+KERNEL_SOURCES = ["paper_2203_12946_amd/csrc/step_kernel.hpp", "paper_2203_12946_amd/csrc/step_f32.hip",
+                  "paper_2203_12946_amd/csrc/lattice.hpp"]
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_d3q27_f32_256.md"
 
 

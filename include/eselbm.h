@@ -38,8 +38,8 @@
  *
  * Ownership: every buffer passed in is device memory owned by the caller.
  * The library never frees caller memory.  It owns only the handle and a
- * small (8 KiB) device block of diagnostic accumulators, which
- * eselbm_create allocates and eselbm_destroy frees.
+ * small (under 10 KiB) device block of diagnostic accumulators and the wall
+ * table, which eselbm_create allocates and eselbm_destroy frees.
  *
  * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
  * stream.  All kernels are enqueued on it asynchronously.  Only
@@ -127,7 +127,7 @@ typedef struct {
 } eselbm_stats;
 
 /* Creates a solver for an nx * ny * nz periodic grid (nz must be 1 for
- * D2Q9).  Allocates the 8 KiB accumulator block on the current device.
+ * D2Q9).  Allocates the accumulator block on the current device.
  * Errors: ESELBM_E_ARG for a NULL out, dims < 1, unknown lattice or dtype,
  * or a grid whose state does not fit a 63-bit index; ESELBM_E_UNSUPPORTED
  * for ny or nz above 65535 (the step launches one block row per (y, z)). */
@@ -156,6 +156,23 @@ eselbm_status eselbm_set_alpha_field(eselbm_handle h, void *alpha);
  * theta = 1/3 (Sec. VII, Eq. nuT): positive where alpha < 2.  NULL disables
  * it.  Cells that were not collided receive NaN. */
 eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut);
+
+/* Bounds the grid by walls (not part of the method; the lid-driven cavity of
+ * Sec. V C uses them).  walls: bit a set (a = 0 x, 1 y, 2 z) bounds axis a by
+ * walls half-way outside its first and last nodes; 0 restores a fully
+ * periodic grid.  velocity: NULL (every wall at rest) or host double
+ * [axis][side][3] wall velocities, side 0 the low and 1 the high wall, each
+ * component below 1 in magnitude.
+ * The walls follow the diffuse boundary rule of Ansumali and Karlin, which
+ * the paper cites for the cavity: a population whose source lies in a wall
+ * is re-emitted by the wall of the first such axis (order x, y, z) as
+ * rho_w feq_i(1, u_wall) (product-form equilibrium), with one rho_w per node
+ * such that the re-emitted populations carry exactly the mass the node's
+ * post-collision populations sent into the walls; the total mass is
+ * conserved.  Not combinable with a body force; the adjoint and the
+ * dissipation loss (periodic differences) reject a walled grid
+ * (ESELBM_E_UNSUPPORTED).  The table is copied to the device synchronously. */
+eselbm_status eselbm_set_walls(eselbm_handle h, int walls, const double *velocity);
 
 /* Registers a body-force density F (device float, [D][nz][ny][nx]) added
  * after the collision as f* += feq(rho, u + F/rho) - feq(rho, u) (exact

@@ -24,7 +24,9 @@ struct eselbm_ctx {
     void *nut_field;
     const float *force;
     const void *last_out;  // output state of the last statistics-enabled step
-    DevStats *dev_stats;   // kStatSlots slots
+    DevStats *dev_stats;   // kStatSlots slots, then the wall table
+    int walls;             // bit a: axis a bounded by diffuse walls
+    double *wall_eq;       // device [2 D][Q], inside the dev_stats allocation
 };
 
 static thread_local std::string g_err;
@@ -70,11 +72,12 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
         delete h;
         return hip_fail(e, "eselbm_create: hipGetDevice");
     }
-    e = hipMalloc((void **)&h->dev_stats, sizeof(DevStats) * kStatSlots);
+    e = hipMalloc((void **)&h->dev_stats, sizeof(DevStats) * kStatSlots + sizeof(double) * kWallEq);
     if (e != hipSuccess) {
         delete h;
         return hip_fail(e, "eselbm_create: hipMalloc");
     }
+    h->wall_eq = (double *)(h->dev_stats + kStatSlots);
     *out = h;
     return ESELBM_OK;
 }
@@ -117,9 +120,50 @@ eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut)
     return ESELBM_OK;
 }
 
+eselbm_status eselbm_set_walls(eselbm_handle h, int walls, const double *velocity)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_walls: NULL handle");
+    const int D = h->g.D, Q = h->g.Q;
+    if (walls < 0 || walls >= (1 << D)) return fail(ESELBM_E_ARG, "eselbm_set_walls: mask has bits beyond the lattice's axes");
+    if (walls && h->force) return fail(ESELBM_E_UNSUPPORTED, "eselbm_set_walls: walls with a body force");
+    // feq_i(1, u) - w_i of every wall, product form (Sec. II): per axis
+    // F(0) = 2 (2 - s) / 3, F(+-1) = (2 s - 1) / 6 +- u / 2, s = sqrt(1 + 3 u^2)
+    double table[kWallEq];
+    std::memset(table, 0, sizeof(table));
+    for (int a = 0; a < D; ++a) {
+        for (int side = 0; side < 2; ++side) {
+            const double *u = velocity ? velocity + 3 * (2 * a + side) : nullptr;
+            double F[3][3], W[3] = {1.0 / 6.0, 2.0 / 3.0, 1.0 / 6.0};
+            for (int b = 0; b < D; ++b) {
+                const double ub = u ? u[b] : 0.0;
+                if (!(std::fabs(ub) < 1.0)) return fail(ESELBM_E_ARG, "eselbm_set_walls: wall speed must be below 1");
+                const double sq = std::sqrt(1.0 + 3.0 * ub * ub);
+                F[b][1] = 2.0 * (2.0 - sq) / 3.0;
+                F[b][0] = (2.0 * sq - 1.0) / 6.0 - 0.5 * ub;
+                F[b][2] = (2.0 * sq - 1.0) / 6.0 + 0.5 * ub;
+            }
+            for (int i = 0; i < Q; ++i) {
+                double pf = 1.0, pw = 1.0;
+                int r = i;
+                for (int b = 0; b < D; ++b) {
+                    pf *= F[b][r % 3];
+                    pw *= W[r % 3];
+                    r /= 3;
+                }
+                table[(2 * a + side) * Q + i] = pf - pw;
+            }
+        }
+    }
+    hipError_t e = hipMemcpy(h->wall_eq, table, sizeof(double) * 2 * D * Q, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_set_walls: copy");
+    h->walls = walls;
+    return ESELBM_OK;
+}
+
 eselbm_status eselbm_set_force(eselbm_handle h, const float *F)
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_set_force: NULL handle");
+    if (F && h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_set_force: forcing with walls");
     if (F && h->dtype != ESELBM_F32) return fail(ESELBM_E_UNSUPPORTED, "eselbm_set_force: forcing needs ESELBM_F32");
     h->force = F;
     return ESELBM_OK;
@@ -156,6 +200,8 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
         sa.g = h->g;
         sa.beta = 1.0 / (2.0 * tau + 1.0);
         sa.force = h->force;
+        sa.walls = h->walls;
+        sa.wall_eq = h->wall_eq;
         sa.alpha_out = last ? h->alpha_field : nullptr;
         sa.nut_out = last ? h->nut_field : nullptr;
         sa.stats = (last && h->stats_on) ? h->dev_stats : nullptr;
@@ -245,6 +291,7 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: force_grad without a registered force");
     if (h->mode == ESELBM_MODE_ELBM || h->mode == ESELBM_MODE_ITERATE1)
         return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the mirror-condition modes");
+    if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: the adjoint is periodic only");
     AdjArgs a;
     a.fn = f_n;
     a.lam_next = lam_next;
@@ -275,6 +322,7 @@ eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *lo
     if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: NULL argument");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: force_grad without a registered force");
+    if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: periodic differences only");
     hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, loss_dev, lam, nullptr, weight,
                                            (float *)force_grad, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_loss: launch");
@@ -287,6 +335,7 @@ eselbm_status eselbm_dissipation_seed(eselbm_handle h, const void *f, void *seed
     if (!h || !f || !seed) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: NULL argument");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: force_grad without a registered force");
+    if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: periodic differences only");
     hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, nullptr, nullptr, seed, weight,
                                            (float *)force_grad, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_seed: launch");

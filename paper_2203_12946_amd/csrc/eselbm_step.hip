@@ -9,368 +9,19 @@
 // one element, so loads stay coalesced; every store is aligned.  Each
 // element of f_in is read exactly once over the whole grid, so there is no
 // reuse for LDS or an XCD-aware block order to capture.
-#include "internal.hpp"
-#include "lattice.hpp"
-
-#include <type_traits>
+#include "step_kernel.hpp"
 
 namespace eselbm {
 
-template <typename V>
-__device__ inline V wave_sum(V v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-__device__ inline unsigned long long wave_min_u64(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long t = __shfl_xor(v, o, 64);
-        v = t < v ? t : v;
-    }
-    return v;
-}
-
-__device__ inline unsigned long long wave_max_u64(unsigned long long v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        unsigned long long t = __shfl_xor(v, o, 64);
-        v = t > v ? t : v;
-    }
-    return v;
-}
-
-// Per-lane diagnostic contributions, reduced over the block and added to
-// one accumulator slot with one atomic per quantity per block.
-struct LaneStats {
-    double mass = 0, mom[3] = {0, 0, 0}, ke = 0, asum = 0;
-    unsigned long long amin = 0x7FF0000000000000ull, amax = 0;
-    unsigned long long n = 0, gated = 0, guard = 0, nonpos = 0, lt2 = 0, exact = 0, iters = 0, fallback = 0;
-};
-
-__device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
-{
-    constexpr int NU = 8;  // counters
-    __shared__ double red_d[4][7];
-    __shared__ unsigned long long red_u[4][NU + 2];
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    double v[7] = {s.mass, s.mom[0], s.mom[1], s.mom[2], s.ke, s.asum, 0.0};
-    unsigned long long c[NU] = {s.n, s.gated, s.guard, s.nonpos, s.lt2, s.exact, s.iters, s.fallback};
-#pragma unroll
-    for (int k = 0; k < 6; ++k) v[k] = wave_sum(v[k]);
-#pragma unroll
-    for (int k = 0; k < NU; ++k) c[k] = wave_sum(c[k]);
-    const unsigned long long mn = wave_min_u64(s.amin), mx = wave_max_u64(s.amax);
-    if (lane == 0) {
-        for (int k = 0; k < 6; ++k) red_d[wid][k] = v[k];
-        for (int k = 0; k < NU; ++k) red_u[wid][k] = c[k];
-        red_u[wid][NU] = mn;
-        red_u[wid][NU + 1] = mx;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        DevStats *st = slot;
-        double t[6] = {0, 0, 0, 0, 0, 0};
-        unsigned long long u[NU] = {0, 0, 0, 0, 0, 0, 0, 0};
-        unsigned long long tmn = red_u[0][NU], tmx = red_u[0][NU + 1];
-        for (int w = 0; w < nw; ++w) {
-            for (int k = 0; k < 6; ++k) t[k] += red_d[w][k];
-            for (int k = 0; k < NU; ++k) u[k] += red_u[w][k];
-            tmn = red_u[w][NU] < tmn ? red_u[w][NU] : tmn;
-            tmx = red_u[w][NU + 1] > tmx ? red_u[w][NU + 1] : tmx;
-        }
-        atomicAdd(&st->mass, t[0]);
-        atomicAdd(&st->mom[0], t[1]);
-        atomicAdd(&st->mom[1], t[2]);
-        atomicAdd(&st->mom[2], t[3]);
-        atomicAdd(&st->kinetic, t[4]);
-        atomicAdd(&st->alpha_sum, t[5]);
-        atomicAdd(&st->n_cells, u[0]);
-        atomicAdd(&st->n_gated, u[1]);
-        atomicAdd(&st->n_guard, u[2]);
-        atomicAdd(&st->n_nonpos, u[3]);
-        atomicAdd(&st->n_lt2, u[4]);
-        atomicAdd(&st->n_exact, u[5]);
-        if (u[6]) atomicAdd(&st->n_iter, u[6]);
-        if (u[7]) atomicAdd(&st->n_fallback, u[7]);
-        atomicMin(&st->alpha_min_bits, tmn);
-        atomicMax(&st->alpha_max_bits, tmx);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// The fused step.
-// ---------------------------------------------------------------------------
-// Per-storage policy: the occupancy floor and the precision of the parts of
-// a single-precision step whose rounding would otherwise dominate the
-// error.  Measured against the oracle rounded to the storage format after
-// every step (the storage floor), on the 64^2, 1024x136 and 3-D parity
-// workloads and on a rough near-inviscid state (|x| up to 0.1, beta 0.9998):
-//  - moment sums rho, j and the equilibrium deviation d = feq - g: their
-//    single-precision rounding is a fixed function of the cell's state, a
-//    bias that accumulates over steps.  With F32-shifted storage (f - w in
-//    float, a floor 20x lower than plain F32) it reaches 10-30x the floor
-//    (2e-6 relative on u after 1000 steps), so both are double there (1-3x
-//    the floor); plain F32 stays within 1.0-2.5x of its floor in single
-//    precision;
-//  - alpha on the exact rational path (cells far from equilibrium): the
-//    update multiplies an error of alpha by x relative to g; single-
-//    precision sums leave 11x the floor after 5 steps of the rough state,
-//    double sums about 1.3x, for both F32 formats;
-//  - alpha beta as a two-term sum (F32-shifted): a rounded 2 beta in every
-//    gated cell would shift the viscosity of the whole flow by its relative
-//    rounding, visible above the shifted floor;
-//  - F16-shifted: storage rounding (1e-3 of the deviation) dwarfs all
-//    arithmetic rounding; F64: every part is double already.
-// The kernel is a stream of Q loads and Q stores per lane and needs several
-// waves per SIMD in flight to cover HBM latency: 4 waves (<= 128 VGPRs) for
-// the single-precision step, 3 where double moments and equilibrium need the
-// registers.
-template <typename S>
-struct StepPolicy {
-    static constexpr int waves = 4;
-    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
-    using Exact = double;
-};
-template <>
-struct StepPolicy<f32s> {
-    static constexpr int waves = 3;
-    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = true;
-    using Exact = double;
-};
-template <>
-struct StepPolicy<_Float16> {
-    static constexpr int waves = 4;
-    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
-    using Exact = float;
-};
-template <>
-struct StepPolicy<double> {
-    static constexpr int waves = 2;
-    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = false;
-    using Exact = double;
-};
-
-// d = feq - g of one cell, with moments and equilibrium in EQ, rounded to T,
-// and its mass and momentum then made exact to rounding.
-template <int D, typename T, typename EQ, typename Dev>
-__device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)[Lat<D>::Q])
-{
-    const EQ rho = EQ(1) + drho, ir = rcp_(rho);
-    const EQ u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : EQ(0)};
-    const Equilibrium<D, EQ> eq(drho, u);
-#pragma unroll
-    for (int i = 0; i < Lat<D>::Q; ++i) {
-        // the stored deviation is formed again rather than kept live since
-        // the moment sums (the empty asm hides it from common-subexpression
-        // elimination and emits nothing)
-        T v = dev(i);
-        asm volatile("" : "+v"(v));
-        d[i] = T(eq.dev(i) - EQ(v));
-    }
-    conserve_moments<D, T>(d);
-}
-
-// The mirror-condition modes iterate over Q logarithms per Newton step:
-// they are ALU-bound, and their loop needs the registers of two waves per
-// SIMD.
-template <typename S, int MODE>
-constexpr int step_waves() { return is_mirror_mode(MODE) ? 2 : StepPolicy<S>::waves; }
-
-template <int D, typename S, int MODE, bool DIAG, bool FORCE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves<S, MODE>()))) void k_step(StepArgs a)
-{
-    using T = typename Storage<S>::T;
-    using Pol = StepPolicy<S>;
-    constexpr int Q = Lat<D>::Q;
-    const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
-    const long long N = a.g.N;
-    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
-    const int x = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
-    const S *__restrict__ fin = (const S *)a.fin;
-    S *__restrict__ fout = (S *)a.fout;
-    const T beta = (T)a.beta;
-
-    LaneStats ls;
-    if (x < nx) {
-        // source coordinate of a population with velocity component c is
-        // (coordinate - c) mod n, indexed here by c + 1
-        const unsigned xs[3] = {x + 1 == nx ? 0u : (unsigned)x + 1u, (unsigned)x,
-                                x == 0 ? (unsigned)nx - 1u : (unsigned)x - 1u};
-        const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
-        const int zs[3] = {z + 1 == nz ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
-        const long long row0 = ((long long)z * ny + y) * nx;
-        const long long cell = row0 + x;
-
-        // p: the stored values as arithmetic type -- the populations g, or
-        // their deviations g - w for shifted storage.  Only p and d = feq - g
-        // stay live as Q-arrays; g and g - w are formed on the fly (g - w is
-        // exact in floating point for g within a factor two of w).
-        // Each population's source row is block-uniform; only the x offset
-        // varies per lane.
-        constexpr bool SH = Storage<S>::kShifted;
-        T p[Q];
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            const int cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1, cx = Lat<D>::c(i, 0) + 1;
-            const S *rowp = fin + ((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
-            p[i] = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
-        }
-        auto dev = [&](int i) { return SH ? p[i] : p[i] - T(Lat<D>::w(i)); };
-
-        // Moments: rho and j feed the equilibrium, and a rounded
-        // single-precision sum is a fixed function of the cell's state, i.e.
-        // a bias on the equilibrium's stress that accumulates over steps;
-        // summed in double where the storage is precise enough to see it.
-        using E = typename std::conditional<Pol::mom_f64, double, T>::type;
-        E drhoE, jE[3];
-        row_moments<D, E>([&](int i) { return E(dev(i)); }, drhoE, jE);
-        // positivity by comparisons (a min over raw loaded values would make
-        // the compiler keep quieted copies of all of them)
-        bool pos = true;
-#pragma unroll
-        for (int i = 0; i < Q; ++i) pos = pos && (gval<D, T, SH>(i, p) > T(0));
-        const T drho = T(drhoE);
-        const T j[3] = {T(jE[0]), T(jE[1]), T(jE[2])};
-        // NaN in any population fails its comparison and propagates into drho
-        const bool ok = pos && abs_(drhoE) < E(1e30);
-        const T rho = T(1) + drho;
-        T alpha = T(0);
-        CellInfo info{0, 0, 0, 0, 0};
-        T dd[Q];
-        // the output is p + (ab + ab_lo) dd; where the policy asks for it,
-        // alpha beta is a two-term sum so that its rounding to single
-        // precision is not a bias shared by every cell (with alpha = 2 in
-        // all gated cells, a rounded 2 beta would shift the viscosity of the
-        // whole flow by its relative rounding)
-        T ab = T(0), ab_lo = T(0);
-        if (ok) {
-            // d = feq - g with the equilibrium in double where the policy asks
-            // for it: the rounding of a single-precision equilibrium is a
-            // fixed function of the cell's state, so it acts as a bias that
-            // accumulates over steps.  The path length stays in T.
-            using EQ = typename std::conditional<Pol::eq_f64, double, T>::type;
-            form_deviation<D, T, EQ>(dev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
-            alpha = path_length<D, T, typename Pol::Exact, MODE, SH>(p, dd, a.beta, info);
-            if (Pol::ab_split) {
-                const double abE = double(alpha) * a.beta;
-                ab = T(abE);
-                ab_lo = T(abE - double(ab));
-            } else {
-                ab = alpha * beta;
-            }
-            if (FORCE) {
-                const T ir = rcp_(rho);
-                const T u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : T(0)};
-                T uf[3] = {u[0], u[1], u[2]};
-#pragma unroll
-                for (int c = 0; c < D; ++c) uf[c] += (T)a.force[(long long)c * N + cell] * ir;
-                const Equilibrium<D, T> eq(drho, u), eqf(drho, uf);
-#pragma unroll
-                for (int i = 0; i < Q; ++i) dd[i] = (ab + ab_lo) * dd[i] + (eqf.dev(i) - eq.dev(i));
-                ab = T(1);
-                ab_lo = T(0);
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) dd[i] = T(0);
-        }
-        // post-collision value p + alpha beta (feq - g) [+ force term]
-#pragma unroll
-        for (int i = 0; i < Q; ++i) {
-            S *orow = fout + ((long long)i * N + row0);
-            const T v = Pol::ab_split || FORCE ? fma_(ab, dd[i], fma_(ab_lo, dd[i], p[i])) : fma_(ab, dd[i], p[i]);
-            Storage<S>::store_nt(lane_ptr(orow, (unsigned)x), v);
-        }
-
-        if (DIAG) {
-            if (a.alpha_out) ((T *)a.alpha_out)[cell] = ok ? alpha : T(__builtin_nan(""));
-            // nu_T = theta (2 - alpha) / (2 alpha beta), theta = 1/3 (Eq. nuT)
-            if (a.nut_out)
-                ((T *)a.nut_out)[cell] = ok ? (T(2) - alpha) * rcp_(T(6) * alpha * beta) : T(__builtin_nan(""));
-            if (ok) {
-                const double r = 1.0 + (double)drho;
-                ls.mass = r;
-                double jj = 0.0;
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    ls.mom[c] = (double)j[c];
-                    jj += (double)j[c] * (double)j[c];
-                }
-                ls.ke = 0.5 * jj / r;
-                ls.asum = (double)alpha;
-                const double ad = (double)alpha;
-                ls.amin = __double_as_longlong(ad);
-                ls.amax = ls.amin;
-                ls.n = 1;
-                ls.gated = info.gated;
-                ls.guard = info.guarded;
-                ls.lt2 = alpha < T(2);
-                ls.exact = info.exact;
-                ls.iters = info.iters;
-                ls.fallback = info.fallback;
-            } else {
-                ls.nonpos = 1;
-            }
-        }
-    }
-    if (DIAG && a.stats) block_reduce_stats(ls, a.stats + (blockIdx.y + blockIdx.z) % kStatSlots);
-}
-
-template <int D, typename S, int MODE>
-static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
-{
-    // (x-block, y, z); the API limits ny and nz to the grid's 65535
-    const int bx = block_x(a.g.nx);
-    if (a.g.ny > 65535 || a.g.nz > 65535) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)((a.g.nx + bx - 1) / bx), (unsigned)a.g.ny, (unsigned)a.g.nz), block(bx);
-    const bool force = a.force != nullptr;
-    if (force) {
-        if constexpr (std::is_same<S, float>::value) {
-            if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, true>), grid, block, 0, s, a);
-            else hipLaunchKernelGGL((k_step<D, S, MODE, false, true>), grid, block, 0, s, a);
-            return hipGetLastError();
-        }
-        return hipErrorInvalidValue;
-    }
-    if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, false>), grid, block, 0, s, a);
-    else hipLaunchKernelGGL((k_step<D, S, MODE, false, false>), grid, block, 0, s, a);
-    return hipGetLastError();
-}
-
-template <int D, typename S>
-static hipError_t launch_step_m(int mode, bool diag, const StepArgs &a, hipStream_t s)
-{
-    switch (mode) {
-    case MODE_HIGHER: return launch_step_t<D, S, MODE_HIGHER>(diag, a, s);
-    case MODE_BGK: return launch_step_t<D, S, MODE_BGK>(diag, a, s);
-    case MODE_LOWER: return launch_step_t<D, S, MODE_LOWER>(diag, a, s);
-    case MODE_ELBM: return launch_step_t<D, S, MODE_ELBM>(diag, a, s);
-    case MODE_ITERATE1: return launch_step_t<D, S, MODE_ITERATE1>(diag, a, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <int D>
-static hipError_t launch_step_d(int dtype, int mode, bool diag, const StepArgs &a, hipStream_t s)
-{
-    switch (dtype) {
-    case 0: return launch_step_m<D, double>(mode, diag, a, s);
-    case 1: return launch_step_m<D, float>(mode, diag, a, s);
-    case 2: return launch_step_m<D, _Float16>(mode, diag, a, s);
-    case 3: return launch_step_m<D, f32s>(mode, diag, a, s);
-    }
-    return hipErrorInvalidValue;
-}
-
 hipError_t launch_step(int dtype, int mode, bool diag, const StepArgs &a, hipStream_t s)
 {
-    return a.g.D == 2 ? launch_step_d<2>(dtype, mode, diag, a, s) : launch_step_d<3>(dtype, mode, diag, a, s);
+    switch (dtype) {
+    case 0: return launch_step_f64(a.g.D, mode, diag, a, s);
+    case 1: return launch_step_f32(a.g.D, mode, diag, a, s);
+    case 2: return launch_step_f16s(a.g.D, mode, diag, a, s);
+    case 3: return launch_step_f32s(a.g.D, mode, diag, a, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 // ---------------------------------------------------------------------------

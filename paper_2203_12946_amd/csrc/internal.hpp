@@ -18,6 +18,7 @@ struct DevStats {
 };
 static_assert(sizeof(DevStats) == 256, "DevStats is two 128-byte lines");
 constexpr int kStatSlots = 32;
+constexpr int kWallEq = 6 * 27;  // doubles of the wall equilibrium table
 
 struct Grid {
     int D, Q, nx, ny, nz;
@@ -30,6 +31,8 @@ struct StepArgs {
     Grid g;
     double beta;
     const float *force;  // [D][N] or null
+    int walls;               // bit a: axis a bounded by diffuse walls, else periodic
+    const double *wall_eq;   // [2 D][Q]: feq_i(1, u_wall) - w_i of wall 2 a + side
     void *alpha_out;     // [N] compute type or null
     void *nut_out;       // [N] compute type or null: nu_T of Eq. nuT
     DevStats *stats;     // kStatSlots slots or null
@@ -37,6 +40,11 @@ struct StepArgs {
 
 // Launchers (return the hipError_t of the launch).
 hipError_t launch_step(int dtype, int mode, bool diag, const StepArgs &a, hipStream_t s);
+// the step for one storage type (step_<type>.hip)
+hipError_t launch_step_f64(int D, int mode, bool diag, const StepArgs &a, hipStream_t s);
+hipError_t launch_step_f32(int D, int mode, bool diag, const StepArgs &a, hipStream_t s);
+hipError_t launch_step_f16s(int D, int mode, bool diag, const StepArgs &a, hipStream_t s);
+hipError_t launch_step_f32s(int D, int mode, bool diag, const StepArgs &a, hipStream_t s);
 hipError_t launch_reset_stats(DevStats *st, hipStream_t s);
 hipError_t launch_init_eq(int dtype, const Grid &g, const double *rho, const double *u, void *f,
                           hipStream_t s);

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "eselbm_set_alpha_field": [_vp, _vp],
     "eselbm_set_nut_field": [_vp, _vp],
     "eselbm_set_force": [_vp, _vp],
+    "eselbm_set_walls": [_vp, ctypes.c_int, _vp],
     "eselbm_init_equilibrium": [_vp, _vp, _vp, _vp, _vp],
     "eselbm_step": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp],
     "eselbm_alpha_stats": [_vp, ctypes.POINTER(Stats), ctypes.c_int, _vp],
@@ -171,6 +172,16 @@ class Solver:
         """Register a [*shape] compute-dtype tensor receiving per-cell nu_T (Eq. nuT)."""
         self._nut = nut
         _check(lib.eselbm_set_nut_field(self._h, _dev(nut, self.compute_dtype, self.cells)))
+
+    def set_walls(self, walls=None, velocity=None):
+        """Diffuse walls: ``walls`` per axis (x, y[, z]) True/False (None: none);
+        ``velocity`` {(axis, side): (ux, uy[, uz])}, side 0 low, 1 high."""
+        mask = 0 if walls is None else sum(1 << a for a, on in enumerate(walls) if on)
+        uw = (ctypes.c_double * 18)()
+        for (a, sd), v in (velocity or {}).items():
+            for k, comp in enumerate(v):
+                uw[(2 * a + sd) * 3 + k] = float(comp)
+        _check(lib.eselbm_set_walls(self._h, mask, ctypes.cast(uw, _vp)))
 
     def set_force(self, F: torch.Tensor | None):
         """Register a [D, *shape] float32 body-force density (F32 storage only)."""
