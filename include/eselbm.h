@@ -76,17 +76,22 @@ typedef enum { ESELBM_F64 = 0, ESELBM_F32 = 1, ESELBM_F16_SHIFTED = 2, ESELBM_F3
  *           step of 1e-5 (single precision) or 1e-9 (double).
  * ITERATE1: one Newton step of that condition from alpha_Lower
  *           (alpha_Iterate1, Sec. V C).
+ * LBGK:     the classic lattice BGK: alpha = 2 with the polynomial
+ *           equilibrium of Eq. histeq, which the paper notes can turn
+ *           negative (for stability comparisons; no gate or guard; no
+ *           forcing, no adjoint).
  * ELBM and ITERATE1 use the gate and guard of App. D; where their result is
  * not a mirror path length in (1, -1/x_min) (no root: the mirror state
  * leaves the polytope of positivity, Sec. III; or a Newton step outside
- * that interval) the cell keeps alpha_Lower.  They are comparison modes of
- * the forward step: eselbm_adjoint_step rejects them. */
+ * that interval) the cell keeps alpha_Lower.  These three are comparison
+ * modes of the forward step: eselbm_adjoint_step rejects them. */
 typedef enum {
     ESELBM_MODE_HIGHER = 0,
     ESELBM_MODE_BGK = 1,
     ESELBM_MODE_LOWER = 2,
     ESELBM_MODE_ELBM = 3,
-    ESELBM_MODE_ITERATE1 = 4
+    ESELBM_MODE_ITERATE1 = 4,
+    ESELBM_MODE_LBGK = 5
 } eselbm_mode;
 typedef enum {
     ESELBM_OK = 0,
@@ -110,7 +115,8 @@ typedef enum {
  *   n_guard   cells where the positivity guard fired (App. D).
  *   n_nonpos  cells with a pre-collision population <= 0 or not finite.
  *             Those cells are streamed but not collided: they keep their
- *             pulled populations.
+ *             pulled populations (in the LBGK mode, which needs no
+ *             logarithm, every finite cell is collided and counted).
  *   n_alpha_lt2  cells with alpha < 2.
  *   n_exact   cells whose path length was evaluated with the exact rational
  *             sums (cells with all |x_i| below 0.02 in single precision and

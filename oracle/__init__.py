@@ -26,7 +26,7 @@ _SRC = _HERE / "eselbm_oracle.c"
 _LIB_PATH = _HERE / "liboracle.so"
 _lib = None
 
-MODES = {"higher": 0, "bgk": 1, "lower": 2, "elbm": 3, "iterate1": 4}
+MODES = {"higher": 0, "bgk": 1, "lower": 2, "elbm": 3, "iterate1": 4, "lbgk": 5}
 
 
 def build() -> pathlib.Path:
@@ -53,6 +53,8 @@ def _load():
     lib.orc_lattice.restype = ctypes.c_int
     lib.orc_equilibrium.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
     lib.orc_equilibrium.restype = None
+    lib.orc_equilibrium_poly.argtypes = [ctypes.c_int, ctypes.c_double, dp, dp]
+    lib.orc_equilibrium_poly.restype = None
     lib.orc_cell_moments.argtypes = [ctypes.c_int, dp, dp, dp]
     lib.orc_cell_moments.restype = None
     lib.orc_path_length.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, ctypes.c_int, dp]
@@ -116,6 +118,15 @@ def equilibrium(D: int, rho: float, u) -> np.ndarray:
     u = _f64(np.resize(np.asarray(u, dtype=np.float64), 3))
     feq = np.zeros(3 ** D)
     lib.orc_equilibrium(D, float(rho), _dp(u), _dp(feq))
+    return feq
+
+
+def equilibrium_poly(D: int, rho: float, u) -> np.ndarray:
+    """Polynomial equilibrium of Eq. histeq for one cell (classic LBGK)."""
+    lib = _load()
+    u = _f64(np.resize(np.asarray(u, dtype=np.float64), 3))
+    feq = np.zeros(3 ** D)
+    lib.orc_equilibrium_poly(D, float(rho), _dp(u), _dp(feq))
     return feq
 
 

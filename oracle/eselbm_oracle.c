@@ -31,7 +31,7 @@
 
 #define ORC_QMAX 27
 
-enum { ORC_HIGHER = 0, ORC_BGK = 1, ORC_LOWER = 2, ORC_ELBM = 3, ORC_ITERATE1 = 4 };
+enum { ORC_HIGHER = 0, ORC_BGK = 1, ORC_LOWER = 2, ORC_ELBM = 3, ORC_ITERATE1 = 4, ORC_LBGK = 5 };
 
 double orc_alpha_elbm(int Q, const double *g, const double *feq);
 double orc_alpha_iterate1(int Q, const double *g, const double *feq);
@@ -91,6 +91,26 @@ void orc_equilibrium(int D, double rho, const double *u, double *feq)
     }
 }
 
+/* The polynomial equilibrium of Eq. histeq (Sec. II), the classic LBGK's:
+ *   f_i^eq = w_i rho [1 + u.c/theta0 + u_a u_b (c_a c_b - theta0 delta_ab)/(2 theta0^2)].
+ * The paper notes that it can turn negative; it serves the classic LBGK
+ * comparison mode only. */
+void orc_equilibrium_poly(int D, double rho, const double *u, double *feq)
+{
+    int c[ORC_QMAX * 3];
+    double w[ORC_QMAX];
+    int Q = orc_lattice(D, c, w);
+    const double th = 1.0 / 3.0;
+    for (int i = 0; i < Q; ++i) {
+        double uc = 0.0, q = 0.0;
+        for (int a = 0; a < D; ++a) uc += u[a] * c[3 * i + a];
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                q += u[a] * u[b] * (c[3 * i + a] * c[3 * i + b] - (a == b ? th : 0.0));
+        feq[i] = w[i] * rho * (1.0 + uc / th + q / (2.0 * th * th));
+    }
+}
+
 /* Moments rho = <f,1>, rho u = <f,c> (Sec. II). */
 void orc_cell_moments(int D, const double *f, double *rho, double *u)
 {
@@ -110,7 +130,7 @@ void orc_cell_moments(int D, const double *f, double *rho, double *u)
  * Path length alpha for one cell (Sec. IV, App. C, App. D).
  *
  * g: pre-collision populations, feq: their equilibrium, beta from tau.
- * mode: ORC_HIGHER (alpha_Higher), ORC_BGK (alpha = 2), ORC_LOWER
+ * mode: ORC_HIGHER (alpha_Higher), ORC_BGK and ORC_LBGK (alpha = 2), ORC_LOWER
  * (alpha_Lower), ORC_ELBM (the converged root of the mirror condition,
  * Sec. III) or ORC_ITERATE1 (one Newton step of it from alpha_Lower,
  * Sec. V C).  All but ORC_BGK use the near-equilibrium gate and the
@@ -153,7 +173,7 @@ int orc_path_length(int Q, const double *g, const double *feq, double beta,
     out[11] = xmax_abs;
 
     double alpha;
-    if (mode == ORC_BGK) {
+    if (mode == ORC_BGK || mode == ORC_LBGK) {
         /* Standard LBGK: the path length is fixed to 2 (Sec. III). */
         alpha = 2.0;
         out[0] = alpha;
@@ -398,7 +418,8 @@ int orc_step(int D, int nx, int ny, int nz, const double *f_in, double *f_out, i
                     }
                     double rho, u[3] = {0.0, 0.0, 0.0};
                     orc_cell_moments(D, g, &rho, u);
-                    orc_equilibrium(D, rho, u, feq);
+                    if (mode == ORC_LBGK) orc_equilibrium_poly(D, rho, u, feq);
+                    else orc_equilibrium(D, rho, u, feq);
                     if (orc_path_length(Q, g, feq, beta, mode, det) != 0) {
                         bad |= 1;
                         continue;
@@ -510,7 +531,8 @@ int orc_step_walls(int D, int nx, int ny, int nz, int walls, const double *uw, c
                     }
                     double rho, u[3] = {0.0, 0.0, 0.0};
                     orc_cell_moments(D, g, &rho, u);
-                    orc_equilibrium(D, rho, u, feq);
+                    if (mode == ORC_LBGK) orc_equilibrium_poly(D, rho, u, feq);
+                    else orc_equilibrium(D, rho, u, feq);
                     if (orc_path_length(Q, g, feq, beta, mode, det) != 0) {
                         bad |= 1;
                         continue;

@@ -94,7 +94,7 @@ eselbm_status eselbm_destroy(eselbm_handle h)
 eselbm_status eselbm_set_mode(eselbm_handle h, int mode)
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_set_mode: NULL handle");
-    if (mode < ESELBM_MODE_HIGHER || mode > ESELBM_MODE_ITERATE1) return fail(ESELBM_E_ARG, "eselbm_set_mode: unknown mode");
+    if (mode < ESELBM_MODE_HIGHER || mode > ESELBM_MODE_LBGK) return fail(ESELBM_E_ARG, "eselbm_set_mode: unknown mode");
     h->mode = mode;
     return ESELBM_OK;
 }
@@ -183,6 +183,7 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
     if (!h) return fail(ESELBM_E_ARG, "eselbm_step: NULL handle");
     if (!f_in || !f_out) return fail(ESELBM_E_ARG, "eselbm_step: NULL state buffer");
     if (nsteps < 1) return fail(ESELBM_E_ARG, "eselbm_step: nsteps must be >= 1");
+    if (h->force && h->mode == ESELBM_MODE_LBGK) return fail(ESELBM_E_UNSUPPORTED, "eselbm_step: forcing in the classic LBGK mode");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_step: tau must be finite and > 0");
     const size_t bytes = (size_t)h->g.Q * (size_t)h->g.N * elem_size(h->dtype);
     const char *a = (const char *)f_in, *b = (const char *)f_out;
@@ -289,8 +290,8 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: tau must be finite and > 0");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: F16 storage has no adjoint");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: force_grad without a registered force");
-    if (h->mode == ESELBM_MODE_ELBM || h->mode == ESELBM_MODE_ITERATE1)
-        return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the mirror-condition modes");
+    if (h->mode == ESELBM_MODE_ELBM || h->mode == ESELBM_MODE_ITERATE1 || h->mode == ESELBM_MODE_LBGK)
+        return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the ELBM, Iterate1 and classic LBGK modes");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: the adjoint is periodic only");
     AdjArgs a;
     a.fn = f_n;

@@ -133,7 +133,9 @@ __device__ inline T quot_(T j, T rho, T r)
     return fma_(r, fma_(-rho, u0, j), u0);
 }
 
-enum Mode { MODE_HIGHER = 0, MODE_BGK = 1, MODE_LOWER = 2, MODE_ELBM = 3, MODE_ITERATE1 = 4 };
+// MODE_LBGK: alpha = 2 with the polynomial equilibrium of Eq. histeq (the
+// classic LBGK, for stability comparisons); the others use the entropic one.
+enum Mode { MODE_HIGHER = 0, MODE_BGK = 1, MODE_LOWER = 2, MODE_ELBM = 3, MODE_ITERATE1 = 4, MODE_LBGK = 5 };
 
 // The two modes that take alpha from the mirror condition (Sec. III).
 __host__ __device__ constexpr bool is_mirror_mode(int m) { return m == MODE_ELBM || m == MODE_ITERATE1; }
@@ -599,7 +601,7 @@ __device__ __attribute__((always_inline)) inline T path_length(const T (&p)[Lat<
     info.exact = 0;
     info.iters = 0;
     info.fallback = 0;
-    if (MODE == MODE_BGK) return T(2);
+    if (MODE == MODE_BGK || MODE == MODE_LBGK) return T(2);
     // the mirror modes start from alpha_Lower
     constexpr int CMODE = is_mirror_mode(MODE) ? MODE_LOWER : MODE;
 

@@ -159,12 +159,15 @@ struct StepPolicy<double> {
 
 // d = feq - g of one cell, with moments and equilibrium in EQ, rounded to T,
 // and its mass and momentum then made exact to rounding.
-template <int D, typename T, typename EQ, typename Dev>
+// With POLY the equilibrium is the polynomial one of Eq. histeq (the classic
+// LBGK mode): feq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)).
+template <int D, typename T, typename EQ, bool POLY, typename Dev>
 __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)[Lat<D>::Q])
 {
     const EQ rho = EQ(1) + drho, ir = rcp_(rho);
     const EQ u[3] = {quot_(j[0], rho, ir), quot_(j[1], rho, ir), D == 3 ? quot_(j[2], rho, ir) : EQ(0)};
     const Equilibrium<D, EQ> eq(drho, u);
+    const EQ uu = u[0] * u[0] + u[1] * u[1] + u[2] * u[2];
 #pragma unroll
     for (int i = 0; i < Lat<D>::Q; ++i) {
         // the stored deviation is formed again rather than kept live since
@@ -172,7 +175,16 @@ __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)
         // elimination and emits nothing)
         T v = dev(i);
         asm volatile("" : "+v"(v));
-        d[i] = T(eq.dev(i) - EQ(v));
+        EQ fe;
+        if (POLY) {
+            EQ cu = EQ(0);
+#pragma unroll
+            for (int a = 0; a < D; ++a) cu += EQ(Lat<D>::c(i, a)) * u[a];
+            fe = EQ(Lat<D>::w(i)) * (drho + rho * (EQ(3) * cu + EQ(4.5) * cu * cu - EQ(1.5) * uu));
+        } else {
+            fe = eq.dev(i);
+        }
+        d[i] = T(fe - EQ(v));
     }
     conserve_moments<D, T>(d);
 }
@@ -316,8 +328,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves<
         for (int i = 0; i < Q; ++i) pos = pos && (gval<D, T, SH>(i, p) > T(0));
         const T drho = T(drhoE);
         const T j[3] = {T(jE[0]), T(jE[1]), T(jE[2])};
-        // NaN in any population fails its comparison and propagates into drho
-        const bool ok = pos && abs_(drhoE) < E(1e30);
+        // NaN in any population fails its comparison and propagates into drho.
+        // The classic LBGK needs no logarithm: it collides every finite cell,
+        // non-positive populations included (they are still counted).
+        const bool finite = abs_(drhoE) < E(1e30);
+        const bool ok = (pos || MODE == MODE_LBGK) && finite;
         const T rho = T(1) + drho;
         T alpha = T(0);
         CellInfo info{0, 0, 0, 0, 0};
@@ -334,7 +349,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves<
             // fixed function of the cell's state, so it acts as a bias that
             // accumulates over steps.  The path length stays in T.
             using EQ = typename std::conditional<Pol::eq_f64, double, T>::type;
-            form_deviation<D, T, EQ>(dev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
+            form_deviation<D, T, EQ, MODE == MODE_LBGK>(dev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
             alpha = path_length<D, T, typename Pol::Exact, MODE, SH>(p, dd, a.beta, info);
             if (Pol::ab_split) {
                 const double abE = double(alpha) * a.beta;
@@ -393,6 +408,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves<
                 ls.exact = info.exact;
                 ls.iters = info.iters;
                 ls.fallback = info.fallback;
+                ls.nonpos = !pos;
             } else {
                 ls.nonpos = 1;
             }
@@ -434,6 +450,7 @@ static hipError_t launch_step_m(int mode, bool diag, const StepArgs &a, hipStrea
     switch (mode) {
     case MODE_HIGHER: return launch_step_t<D, S, MODE_HIGHER>(diag, a, s);
     case MODE_BGK: return launch_step_t<D, S, MODE_BGK>(diag, a, s);
+    case MODE_LBGK: return launch_step_t<D, S, MODE_LBGK>(diag, a, s);
     case MODE_LOWER: return launch_step_t<D, S, MODE_LOWER>(diag, a, s);
     case MODE_ELBM: return launch_step_t<D, S, MODE_ELBM>(diag, a, s);
     case MODE_ITERATE1: return launch_step_t<D, S, MODE_ITERATE1>(diag, a, s);

@@ -16,12 +16,12 @@ _LIB_PATH = pathlib.Path(__file__).resolve().parent / "libeselbm.so"
 
 D2Q9, D3Q27 = 0, 1
 F64, F32, F16_SHIFTED, F32_SHIFTED = 0, 1, 2, 3
-MODE_HIGHER, MODE_BGK, MODE_LOWER, MODE_ELBM, MODE_ITERATE1 = 0, 1, 2, 3, 4
+MODE_HIGHER, MODE_BGK, MODE_LOWER, MODE_ELBM, MODE_ITERATE1, MODE_LBGK = 0, 1, 2, 3, 4, 5
 OK, E_ARG, E_UNSUPPORTED, E_HIP, E_NONPOSITIVE = 0, 1, 2, 3, 4
 
 DTYPES = {"f64": F64, "f32": F32, "f16s": F16_SHIFTED, "f32s": F32_SHIFTED}
 MODES = {"higher": MODE_HIGHER, "bgk": MODE_BGK, "lower": MODE_LOWER, "elbm": MODE_ELBM,
-         "iterate1": MODE_ITERATE1}
+         "iterate1": MODE_ITERATE1, "lbgk": MODE_LBGK}
 LATTICES = {"D2Q9": D2Q9, "D3Q27": D3Q27}
 TORCH_STORAGE = {F64: torch.float64, F32: torch.float32, F16_SHIFTED: torch.float16,
                  F32_SHIFTED: torch.float32}

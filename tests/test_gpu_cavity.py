@@ -15,6 +15,12 @@ concludes from the tables: alpha_Higher and alpha_ELBM differ insignificantly
 and the bands shrink as the grid is refined, and the one-step iterate from
 alpha_Lower is closer to the ELBM root than alpha_Lower.  The norms are means
 over cells (L1, L2) and the maximum (Linf); the paper does not define them.
+
+Stability (the paper: LBGK unstable on 64^2 to 128^2, stable on 256^2, the
+entropic path lengths stable on all): the classic LBGK, alpha = 2 with the
+polynomial equilibrium of Eq. histeq, and alpha = 2 with the entropic
+equilibrium, against alpha_Higher on the same cavity.  A run fails when a
+population turns non-positive.
 """
 import math
 import sys
@@ -38,11 +44,11 @@ def _log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def _cavity(es, N, dtype="f32", conv_times=100, Re=5000.0, Ma=0.05):
+def _cavity(es, N, dtype="f32", conv_times=100, Re=5000.0, Ma=0.05, mode="higher"):
     U = Ma / math.sqrt(3.0)
     tau = 3.0 * U * N / Re  # nu = U N / Re, tau = nu / theta0
     steps = int(round(conv_times * N / U))
-    s = es.Solver("D2Q9", (N, N), dtype=dtype, mode="higher")
+    s = es.Solver("D2Q9", (N, N), dtype=dtype, mode=mode)
     s.set_walls([True, True], {(1, 1): (U, 0.0)})
     a = s.init_equilibrium(torch.ones((N, N), dtype=torch.float64, device="cuda"),
                            torch.zeros((2, N, N), dtype=torch.float64, device="cuda"))
@@ -95,3 +101,58 @@ def test_cavity_alpha_tables(es):
     assert rows[64]["HE"][0] > rows[96]["HE"][0] > rows[128]["HE"][0]
     assert rows[64]["HE"][1] > rows[96]["HE"][1] > rows[128]["HE"][1]
     assert rows[64]["bandH"] > rows[96]["bandH"] > rows[128]["bandH"]
+
+
+def _first_failure(es, N, mode, conv_times, every=10):
+    """First check (every `every` steps) at which some pre-collision
+    population was non-positive, and the step at which the fields stopped
+    being finite, each None if it did not happen.  Once a population turns
+    negative the classic LBGK blows up within a few hundred steps, so a
+    check every few steps does not miss a failure."""
+    U = 0.05 / math.sqrt(3.0)
+    tau = 3.0 * U * N / 5000.0
+    steps = int(round(conv_times * N / U))
+    s = es.Solver("D2Q9", (N, N), dtype="f64", mode=mode)
+    s.set_walls([True, True], {(1, 1): (U, 0.0)})
+    a = s.init_equilibrium(torch.ones((N, N), dtype=torch.float64, device="cuda"),
+                           torch.zeros((2, N, N), dtype=torch.float64, device="cuda"))
+    b = s.empty_state()
+    s.set_stats(True)
+    first_nonpos = None
+    n = 0
+    while n < steps:
+        k = min(every, steps - n)
+        s.step(a, b, k, tau)
+        a, b = b, a
+        n += k
+        st = s.stats()
+        if st["n_nonpos"] > 0 and first_nonpos is None:
+            first_nonpos = n
+            if mode != "lbgk":
+                # the entropic modes do not collide such cells; stop here
+                return first_nonpos, None
+        if not (math.isfinite(st["kinetic"]) and abs(st["kinetic"]) < 1e30):
+            return first_nonpos, n
+        if first_nonpos is not None and n >= first_nonpos + 2000:
+            return first_nonpos, None
+    return first_nonpos, None
+
+
+def test_cavity_stability(es):
+    """Classic LBGK and alpha = 2 with the entropic equilibrium lose
+    positivity on the coarsest grid; alpha_Higher stays positive on every
+    grid.  Runs of 100 convection times (10 on 256^2)."""
+    res = {}
+    U = 0.05 / math.sqrt(3.0)
+    for N, conv in ((64, 100), (96, 100), (128, 100), (256, 10)):
+        for mode in ("lbgk", "bgk", "higher"):
+            res[(N, mode)] = _first_failure(es, N, mode, conv)
+            f, nan = res[(N, mode)]
+            _log(f"[cavity stability {N}x{N} {mode}] "
+                 + (f"non-positive population by step {f} ({f * U / N:.2f} convection times)"
+                    + (f", fields non-finite at step {nan}" if nan else "") if f else
+                    f"positive for {conv} convection times"))
+    assert res[(64, "lbgk")][0] is not None and res[(64, "bgk")][0] is not None
+    for N in (64, 96, 128, 256):
+        assert res[(N, "higher")][0] is None
+    assert res[(256, "lbgk")][0] is None

@@ -85,7 +85,7 @@ def _cavity_state(D, shape, seed):
     return oracle.init_equilibrium(np.ones(shape), u)
 
 
-@pytest.mark.parametrize("mode", ["higher", "bgk", "elbm"])
+@pytest.mark.parametrize("mode", ["higher", "bgk", "elbm", "lbgk"])
 @pytest.mark.parametrize("D,shape", [(2, (24, 32)), (3, (10, 12, 14))])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
 def test_cavity_parity(es, D, shape, mode, dtype):

@@ -10,6 +10,7 @@ import numpy as np
 import pytest
 
 import oracle
+from paper_2203_12946_amd import workloads as W
 from tests._states import mixed_mirror_lattice, null_space_direction, perturbed_state
 
 THETA0 = 1.0 / 3.0
@@ -660,3 +661,34 @@ def test_walls_couette_profile(tau):
     assert np.max(np.abs(v[0] - exact[:, None])) < 1e-12
     assert np.max(np.abs(v[1])) < 1e-11
     assert np.max(np.abs(r - 1)) < 1e-11
+
+
+# --------------------------------------------------------------------------
+# The classic LBGK comparison mode: polynomial equilibrium (Eq. histeq)
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("D", [1, 2, 3])
+def test_polynomial_equilibrium_moments(D):
+    """Eq. histeq reproduces rho, rho u and the Maxwellian second moment
+    rho (u u + theta0 I) exactly on the D1Q3 product lattices (the weight
+    moment conditions of Sec. II), and can turn negative at large u (the
+    paper's reason for the entropic form)."""
+    c, _ = oracle.lattice(D)
+    c = c[:, :D].astype(float)
+    rng = np.random.default_rng(60 + D)
+    for _ in range(5):
+        rho = 1 + 0.2 * rng.standard_normal()
+        u = 0.15 * rng.standard_normal(D)
+        f = oracle.equilibrium_poly(D, rho, u)
+        assert abs(f.sum() - rho) < 1e-14
+        np.testing.assert_allclose(c.T @ f, rho * u, atol=1e-14)
+        P = np.einsum("i,ia,ib->ab", f, c, c)
+        np.testing.assert_allclose(P, rho * (np.outer(u, u) + np.eye(D) / 3), atol=1e-14)
+    assert oracle.equilibrium_poly(D, 1.0, [0.9] + [0.0] * (D - 1)).min() < 0
+
+
+def test_lbgk_mode_conserves_and_uses_alpha_two():
+    rho, u = W.taylor_green_2d(16, u0=0.05)
+    f = oracle.init_equilibrium(rho, u)
+    out, alpha, (ng, nd, nn) = oracle.step(f, 3, 0.02, mode="lbgk", want_alpha=True)
+    assert np.all(alpha == 2.0) and ng == 0 and nd == 0
+    assert abs(out.sum() - f.sum()) < 1e-12 * f.sum()
