@@ -142,6 +142,9 @@ class Solver:
         self.compute_dtype = TORCH_COMPUTE[self.dtype_code]
         self.device = torch.device("cuda", torch.cuda.current_device() if device is None else device)
         self._h = _vp()
+        # held by the instance: at interpreter exit the module global may be
+        # cleared before the last solver is collected
+        self._lib = lib
         with torch.cuda.device(self.device):
             _check(lib.eselbm_create(ctypes.byref(self._h), LATTICES[lattice], nx, ny, nz, self.dtype_code))
         self._alpha = None
@@ -151,8 +154,8 @@ class Solver:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h is not None and h.value:
-            lib.eselbm_destroy(h)
+        if h is not None and h.value and getattr(self, "_lib", None) is not None:
+            self._lib.eselbm_destroy(h)
             self._h = _vp()
 
     # ---- configuration --------------------------------------------------
