@@ -188,7 +188,13 @@ def alpha_iterate1(g, feq) -> float:
 
 
 def _grid(f):
-    """(D, nx, ny, nz) of an SoA state shaped [Q, ny, nx] or [Q, nz, ny, nx]."""
+    """(D, nx, ny, nz) of an SoA state shaped [3, nx], [9, ny, nx] or
+    [27, nz, ny, nx]."""
+    if f.ndim == 2:
+        Q, nx = f.shape
+        if Q != 3:
+            raise ValueError("a 1-D state must have 3 populations")
+        return 1, nx, 1, 1
     if f.ndim == 3:
         Q, ny, nx = f.shape
         if Q != 9:
@@ -199,7 +205,7 @@ def _grid(f):
         if Q != 27:
             raise ValueError("a 3-D state must have 27 populations")
         return 3, nx, ny, nz
-    raise ValueError("state must be [Q,ny,nx] or [Q,nz,ny,nx]")
+    raise ValueError("state must be [Q,nx], [Q,ny,nx] or [Q,nz,ny,nx]")
 
 
 def step(f, nsteps: int, tau: float, mode: str = "higher", force=None,
