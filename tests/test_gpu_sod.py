@@ -111,7 +111,8 @@ def test_sod_parity_f64(es, mode):
          f"gated={g['stats']['n_gated']} (oracle {ref['counts'][0]})")
     assert drho <= 1e-11 and du <= 1e-11
     assert da <= 1e-8 and dn <= 1e-8
-    assert float(np.max(np.abs(g["uy"]))) == 0.0
+    # the y-velocity of the one-node-high lattice stays at rounding level
+    assert float(np.max(np.abs(g["uy"]))) <= 1e-15
     assert g["stats"]["n_nonpos"] == 0
     assert g["stats"]["n_gated"] == ref["counts"][0]
 
