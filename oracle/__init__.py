@@ -75,6 +75,13 @@ def _load():
     lib.orc_step_walls.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
                                    dp, ctypes.c_int, ctypes.c_double, ctypes.c_int, dp, llp]
     lib.orc_step_walls.restype = ctypes.c_int
+    lib.orc_esbgk_cpr.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.orc_esbgk_cpr.restype = ctypes.c_double
+    lib.orc_quasi_equilibrium.argtypes = [ctypes.c_int, dp, dp, ctypes.c_double, dp, ip]
+    lib.orc_quasi_equilibrium.restype = ctypes.c_int
+    lib.orc_step_esbgk.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, dp, dp,
+                                   ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, llp]
+    lib.orc_step_esbgk.restype = ctypes.c_int
     lib.orc_init_equilibrium.argtypes = [ctypes.c_int, ctypes.c_longlong, dp, dp, dp]
     lib.orc_init_equilibrium.restype = None
     lib.orc_moments.argtypes = [ctypes.c_int, ctypes.c_longlong, dp, dp, dp]
@@ -229,6 +236,47 @@ def step(f, nsteps: int, tau: float, mode: str = "higher", force=None,
                       counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
     if rc == -1:
         raise OracleError("non-positive or non-finite pre-collision population")
+    if rc != 0:
+        raise MemoryError("oracle allocation failed")
+    if want_alpha:
+        return out, alpha, (int(counts[0]), int(counts[1]), int(counts[2]))
+    return out
+
+
+def esbgk_cpr(tau1: float, prandtl: float) -> float:
+    """The ES-BGK stress factor c_Pr = (1 - 1/Pr) / (1 + 1/(2 tau1 Pr))."""
+    return float(_load().orc_esbgk_cpr(float(tau1), float(prandtl)))
+
+
+def quasi_equilibrium(g, feq, cpr: float):
+    """(f^QE, converged, Newton steps) of one cell: the minimiser of H with the
+    mass and momentum of g and pressure tensor P(feq) + cpr (P(g) - P(feq))."""
+    lib = _load()
+    g = _f64(g)
+    feq = _f64(feq)
+    D = {3: 1, 9: 2, 27: 3}[g.size]
+    out = np.empty_like(g)
+    it = ctypes.c_int(0)
+    rc = lib.orc_quasi_equilibrium(D, _dp(g), _dp(feq), float(cpr), _dp(out), ctypes.byref(it))
+    return out, rc == 0, int(it.value)
+
+
+def step_esbgk(f, nsteps: int, tau1: float, prandtl: float, mode: str = "higher",
+               want_alpha: bool = False):
+    """Periodic entropic ES-BGK steps (mode higher, lower or bgk).  With
+    ``want_alpha`` returns ``(state, alpha, (n_gated, n_guarded, n_qe_fallback))``."""
+    lib = _load()
+    f = _f64(f)
+    D, nx, ny, nz = _grid(f)
+    out = np.empty_like(f)
+    alpha = np.empty(f.shape[1:]) if want_alpha else None
+    counts = np.zeros(3, dtype=np.int64)
+    rc = lib.orc_step_esbgk(D, nx, ny, nz, _dp(f), _dp(out), int(nsteps), float(tau1), float(prandtl),
+                            MODES[mode], _dp(alpha), counts.ctypes.data_as(ctypes.POINTER(ctypes.c_longlong)))
+    if rc == -1:
+        raise OracleError("non-positive or non-finite pre-collision population")
+    if rc == -3:
+        raise ValueError("ES-BGK steps take mode higher, lower or bgk")
     if rc != 0:
         raise MemoryError("oracle allocation failed")
     if want_alpha:

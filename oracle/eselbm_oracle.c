@@ -560,6 +560,203 @@ int orc_step_walls(int D, int nx, int ny, int nz, int walls, const double *uw, c
     return bad ? -1 : 0;
 }
 
+/* ---------------------------------------------------------------------
+ * Entropic lattice ES-BGK (the section on the exact path length of the
+ * entropic lattice ES-BGK model).
+ *
+ * The quasi-equilibrium f^QE minimises H over the states that have the mass
+ * and momentum of g and the pressure tensor
+ *   P(f^QE) = P(f^eq) + c_Pr sigma(g),   sigma(g) = P(g) - P(f^eq),
+ *   c_Pr = (1 - 1/Pr) / (1 + 1/(2 tau1 Pr))       (time step 1),
+ * P(f) = sum_i f_i c_i c_i.  The paper writes the Maxwellian pressure
+ * rho u u + rho theta I where P(f^eq) stands here: on the lattice the
+ * equilibrium's own pressure tensor takes its place, so that f^QE = f^eq
+ * when Pr = 1 or sigma = 0 (the quasi-equilibrium reduces to the
+ * equilibrium, as the paper requires), and sigma is the full deviation,
+ * trace included (the isothermal lattice has no energy equation to remove
+ * it).
+ *
+ * The minimiser is f_i^QE = w_i exp(lambda . phi_i) over the basis
+ * phi_i = (1, c_ia, c_ia c_ib for a <= b), K = 1 + D + D(D+1)/2 functions.
+ * Its multipliers are found numerically, as the paper does: Newton's method
+ * on the moment equations, written for the correction delta in
+ * f^QE = f^eq exp(delta . phi) (f^eq is the minimiser without the pressure
+ * constraint, so delta = 0 is the start), with residual
+ *   R_k = sum_i f_i^eq (exp(delta . phi_i) - 1) phi_ik - T_k,
+ * T = (0, 0, c_Pr sigma), Jacobian sum_i f_i^QE phi_ik phi_il, solved by
+ * Cholesky.  Converged when no component of the Newton step exceeds 1e-13.
+ * Returns 0, or -1 when the iteration does not converge (the target
+ * pressure tensor is one no positive state carries); fqe is then feq.
+ * iters (may be NULL) receives the number of Newton steps.
+ * ------------------------------------------------------------------- */
+static int qe_basis(int D, const int *c, int i, double *phi)
+{
+    int k = 0;
+    phi[k++] = 1.0;
+    for (int a = 0; a < D; ++a) phi[k++] = c[3 * i + a];
+    for (int a = 0; a < D; ++a)
+        for (int b = a; b < D; ++b) phi[k++] = (double)(c[3 * i + a] * c[3 * i + b]);
+    return k;
+}
+
+/* Solve A x = r for a symmetric positive definite n x n A (row-major), by
+ * Cholesky.  Returns -1 if A is not positive definite. */
+static int cholesky_solve(int n, double *A, const double *r, double *x)
+{
+    for (int j = 0; j < n; ++j) {
+        double d = A[j * n + j];
+        for (int k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+        if (!(d > 0.0)) return -1;
+        A[j * n + j] = sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double v = A[i * n + j];
+            for (int k = 0; k < j; ++k) v -= A[i * n + k] * A[j * n + k];
+            A[i * n + j] = v / A[j * n + j];
+        }
+    }
+    double y[16];
+    for (int i = 0; i < n; ++i) {
+        double v = r[i];
+        for (int k = 0; k < i; ++k) v -= A[i * n + k] * y[k];
+        y[i] = v / A[i * n + i];
+    }
+    for (int i = n - 1; i >= 0; --i) {
+        double v = y[i];
+        for (int k = i + 1; k < n; ++k) v -= A[k * n + i] * x[k];
+        x[i] = v / A[i * n + i];
+    }
+    return 0;
+}
+
+double orc_esbgk_cpr(double tau1, double prandtl)
+{
+    return (1.0 - 1.0 / prandtl) / (1.0 + 1.0 / (2.0 * tau1 * prandtl));
+}
+
+int orc_quasi_equilibrium(int D, const double *g, const double *feq, double cpr, double *fqe, int *iters)
+{
+    int c[ORC_QMAX * 3];
+    double w[ORC_QMAX];
+    int Q = orc_lattice(D, c, w);
+    double phi[ORC_QMAX][10];
+    int K = 0;
+    for (int i = 0; i < Q; ++i) K = qe_basis(D, c, i, phi[i]);
+    /* target increments of the moments over those of feq */
+    double T[10] = {0};
+    for (int k = 1 + D; k < K; ++k) {
+        double sig = 0.0;
+        for (int i = 0; i < Q; ++i) sig += (g[i] - feq[i]) * phi[i][k];
+        T[k] = cpr * sig;
+    }
+    double delta[10] = {0};
+    int it, conv = 0;
+    for (it = 0; it < 50 && !conv; ++it) {
+        double R[10] = {0}, J[100] = {0}, step[10];
+        for (int i = 0; i < Q; ++i) {
+            double arg = 0.0;
+            for (int k = 0; k < K; ++k) arg += delta[k] * phi[i][k];
+            double fq = feq[i] * exp(arg);
+            double r = feq[i] * expm1(arg);
+            for (int k = 0; k < K; ++k) {
+                R[k] += r * phi[i][k];
+                for (int l = 0; l < K; ++l) J[k * K + l] += fq * phi[i][k] * phi[i][l];
+            }
+        }
+        double mr[10];
+        for (int k = 0; k < K; ++k) mr[k] = -(R[k] - T[k]);
+        if (cholesky_solve(K, J, mr, step) != 0) break;
+        double mx = 0.0;
+        for (int k = 0; k < K; ++k) {
+            if (!isfinite(step[k])) { mx = INFINITY; break; }
+            delta[k] += step[k];
+            mx = fabs(step[k]) > mx ? fabs(step[k]) : mx;
+        }
+        if (!(mx < 1e3)) break;
+        conv = mx <= 1e-13;
+    }
+    if (iters) *iters = it;
+    if (!conv) {
+        for (int i = 0; i < Q; ++i) fqe[i] = feq[i];
+        return -1;
+    }
+    for (int i = 0; i < Q; ++i) {
+        double arg = 0.0;
+        for (int k = 0; k < K; ++k) arg += delta[k] * phi[i][k];
+        fqe[i] = feq[i] * exp(arg);
+    }
+    return 0;
+}
+
+/* Whole-lattice ES-BGK steps, periodic: as orc_step, with f^QE in place of
+ * f^eq in the collision, f* = g + alpha beta (f^QE - g), beta = 1/(2 tau1 + 1),
+ * and alpha from x = f^QE/g - 1 by the same path length (the paper: the
+ * path length keeps its closed form; the term the pressure multipliers add
+ * to Delta H is left out).  mode: ORC_HIGHER, ORC_LOWER or ORC_BGK.
+ * counts: [gated, guarded, cells whose quasi-equilibrium did not converge
+ * and used f^eq].  Returns 0, -1 on a non-positive population, -3 on an
+ * unsupported mode. */
+int orc_step_esbgk(int D, int nx, int ny, int nz, const double *f_in, double *f_out, int nsteps,
+                   double tau1, double prandtl, int mode, double *alpha_out, long long *counts)
+{
+    if (mode != ORC_HIGHER && mode != ORC_LOWER && mode != ORC_BGK) return -3;
+    int c[ORC_QMAX * 3];
+    double w[ORC_QMAX];
+    int Q = orc_lattice(D, c, w);
+    long long N = (long long)nx * ny * nz;
+    double beta = 1.0 / (2.0 * tau1 + 1.0);
+    double cpr = orc_esbgk_cpr(tau1, prandtl);
+    double *cur = (double *)malloc(sizeof(double) * Q * N);
+    double *nxt = (double *)malloc(sizeof(double) * Q * N);
+    if (!cur || !nxt) { free(cur); free(nxt); return -2; }
+    memcpy(cur, f_in, sizeof(double) * Q * N);
+    int bad = 0;
+    long long ngated = 0, nguard = 0, nfall = 0;
+    for (int s = 0; s < nsteps; ++s) {
+        int last = (s == nsteps - 1);
+        long long sg = 0, sd = 0, sf = 0;
+#pragma omp parallel for collapse(2) reduction(+ : sg, sd, sf) reduction(| : bad)
+        for (int z = 0; z < nz; ++z) {
+            for (int y = 0; y < ny; ++y) {
+                for (int xx = 0; xx < nx; ++xx) {
+                    long long cell = ((long long)z * ny + y) * nx + xx;
+                    double g[ORC_QMAX], feq[ORC_QMAX], fqe[ORC_QMAX], det[16];
+                    for (int i = 0; i < Q; ++i) {
+                        long long sx = wrap(xx - c[3 * i + 0], nx);
+                        long long sy = wrap(y - c[3 * i + 1], ny);
+                        long long sz = wrap(z - c[3 * i + 2], nz);
+                        g[i] = cur[(long long)i * N + (sz * ny + sy) * nx + sx];
+                    }
+                    double rho, u[3] = {0.0, 0.0, 0.0};
+                    orc_cell_moments(D, g, &rho, u);
+                    orc_equilibrium(D, rho, u, feq);
+                    int fell = orc_quasi_equilibrium(D, g, feq, cpr, fqe, NULL) != 0;
+                    if (orc_path_length(Q, g, fqe, beta, mode, det) != 0) {
+                        bad |= 1;
+                        continue;
+                    }
+                    double alpha = det[0];
+                    for (int i = 0; i < Q; ++i)
+                        nxt[(long long)i * N + cell] = g[i] + alpha * beta * (fqe[i] - g[i]);
+                    if (last) {
+                        if (alpha_out) alpha_out[cell] = alpha;
+                        sg += det[12] > 0.0;
+                        sd += det[13] > 0.0;
+                        sf += fell;
+                    }
+                }
+            }
+        }
+        if (bad) break;
+        if (last) { ngated = sg; nguard = sd; nfall = sf; }
+        double *t = cur; cur = nxt; nxt = t;
+    }
+    if (!bad) memcpy(f_out, cur, sizeof(double) * Q * N);
+    free(cur);
+    free(nxt);
+    if (counts) { counts[0] = ngated; counts[1] = nguard; counts[2] = nfall; }
+    return bad ? -1 : 0;
+}
+
 /* Equilibrium state f = feq(rho, u) for every cell; rho [N], u [D][N]. */
 void orc_init_equilibrium(int D, long long N, const double *rho, const double *u, double *f)
 {

@@ -797,3 +797,146 @@ def test_sod_oscillations_and_entropy():
             H1 = oracle.H(f)
             assert H1 <= H0
             H0 = H1
+
+
+# --------------------------------------------------------------------------
+# Entropic lattice ES-BGK (the section on the ES-BGK model's path length)
+# --------------------------------------------------------------------------
+def _basis(D):
+    c, _ = oracle.lattice(D)
+    c = c[:, :D].astype(float)
+    cols = [np.ones(len(c))] + [c[:, a] for a in range(D)]
+    cols += [c[:, a] * c[:, b] for a in range(D) for b in range(a, D)]
+    return c, np.array(cols).T
+
+
+def _P(f, c):
+    return np.einsum("i,ia,ib->ab", f, c, c)
+
+
+@pytest.mark.parametrize("D", [2, 3])
+@pytest.mark.parametrize("Pr", [0.71, 2.0])
+def test_quasi_equilibrium_is_the_constrained_minimiser(D, Pr):
+    """f^QE has the mass and momentum of g and the pressure tensor
+    P(feq) + c_Pr (P(g) - P(feq)); log(f^QE / w) lies in the span of
+    (1, c, cc) (the stationarity condition of H under those constraints, a
+    strictly convex problem, so f^QE is its unique minimiser); and moving
+    along any direction that keeps the constraints raises H."""
+    rng = np.random.default_rng(70 + D)
+    c, B = _basis(D)
+    _, w = oracle.lattice(D)
+    for tau1 in (0.01, 0.3):
+        cpr = oracle.esbgk_cpr(tau1, Pr)
+        assert abs(cpr - (1 - 1 / Pr) / (1 + 1 / (2 * tau1 * Pr))) < 1e-15
+        for eps in (1e-3, 0.05):
+            g, feq = perturbed_state(D, eps, rng)
+            fq, ok, it = oracle.quasi_equilibrium(g, feq, cpr)
+            assert ok and it <= 8
+            assert abs(fq.sum() - g.sum()) < 1e-14
+            assert np.max(np.abs(c.T @ fq - c.T @ g)) < 1e-14
+            target = _P(feq, c) + cpr * (_P(g, c) - _P(feq, c))
+            assert np.max(np.abs(_P(fq, c) - target)) < 1e-14
+            coef = np.linalg.lstsq(B, np.log(fq / w), rcond=None)[0]
+            assert np.max(np.abs(B @ coef - np.log(fq / w))) < 1e-13
+            # constraint-preserving directions: orthogonal to every basis column
+            q, _ = np.linalg.qr(B)
+            Hq = float(np.sum(fq * np.log(fq / w)))
+            for _ in range(5):
+                v = rng.standard_normal(len(w))
+                v -= q @ (q.T @ v)
+                v *= 1e-4 * fq.min() / np.abs(v).max()
+                assert np.sum((fq + v) * np.log((fq + v) / w)) > Hq
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_quasi_equilibrium_reduces_to_equilibrium(D):
+    """c_Pr = 0 (Pr = 1) or g = feq (no stress) give f^QE = feq."""
+    rng = np.random.default_rng(80 + D)
+    g, feq = perturbed_state(D, 0.05, rng)
+    fq, ok, _ = oracle.quasi_equilibrium(g, feq, 0.0)
+    assert ok and np.max(np.abs(fq - feq)) < 1e-16
+    fq, ok, _ = oracle.quasi_equilibrium(feq, feq, oracle.esbgk_cpr(0.1, 0.71))
+    assert ok and np.max(np.abs(fq - feq)) < 1e-16
+
+
+@pytest.mark.parametrize("mode", ["higher", "bgk"])
+def test_esbgk_at_prandtl_one_is_the_standard_step(mode):
+    rho, u = W.taylor_green_2d(16, u0=0.05)
+    f = oracle.init_equilibrium(rho, u)
+    a = oracle.step(f, 20, 0.02, mode=mode)
+    b = oracle.step_esbgk(f, 20, 0.02, 1.0, mode=mode)
+    assert np.max(np.abs(a - b)) < 1e-15
+
+
+@pytest.mark.parametrize("Pr", [0.5, 0.71, 2.0])
+@pytest.mark.parametrize("mode", ["bgk", "higher"])
+def test_esbgk_viscosity_follows_prandtl(Pr, mode):
+    """The shear viscosity of the ES-BGK lattice is nu = tau1 theta Pr: a
+    Taylor-Green vortex decays at 4 nu k^2.  (On the isothermal lattice the
+    Prandtl number acts through the viscosity alone; at alpha = 2 the stress
+    relaxes by 1 - 2 beta (1 - c_Pr) per step, i.e. with tau1 Pr in place of
+    tau1.)"""
+    n, tau1 = 32, 0.05
+    rho, u = W.taylor_green_2d(n, u0=0.02)
+    f = oracle.init_equilibrium(rho, u)
+    k = 2 * math.pi / n
+
+    def ke(s):
+        r, v = oracle.moments(s)
+        return 0.5 * float((r * (v ** 2).sum(0)).sum())
+
+    a = oracle.step_esbgk(f, 100, tau1, Pr, mode=mode)
+    b = oracle.step_esbgk(a, 200, tau1, Pr, mode=mode)
+    nu = -math.log(ke(b) / ke(a)) / 200 / (4 * k * k)
+    assert abs(nu / (tau1 * Pr / 3.0) - 1) < 2e-3
+
+
+def test_esbgk_entropy_per_cell():
+    """Delta H of one ES-BGK collision with alpha_Higher, exactly, over random
+    cells near and far from equilibrium.  Delta H is the path-length part the
+    closed form keeps non-positive plus the term of the pressure multipliers,
+    -alpha beta (1 - c_Pr) Lambda : sigma, which the paper leaves out as
+    entropy production.  That term has the sign of -c_Pr: negative for
+    Pr > 1, but positive for Pr < 1 (Lambda follows c_Pr sigma).  Pinned:
+    Delta H <= 0 in every cell for Pr > 1; for Pr < 1 the term is positive,
+    and in this sample the whole Delta H still stays <= 0."""
+    rng = np.random.default_rng(91)
+    for D in (2, 3):
+        c, _ = _basis(D)
+        _, w = oracle.lattice(D)
+        for Pr in (0.71, 2.0):
+            for tau1 in (1e-4, 0.01, 0.3):
+                beta = 1.0 / (2 * tau1 + 1)
+                cpr = oracle.esbgk_cpr(tau1, Pr)
+                for _ in range(60):
+                    eps = 10 ** rng.uniform(-3, -0.8)
+                    g, feq = perturbed_state(D, eps, rng, u=0.1 * rng.standard_normal(D))
+                    if g.min() <= 0:
+                        continue
+                    fq, ok, _ = oracle.quasi_equilibrium(g, feq, cpr)
+                    assert ok
+                    a = oracle.path_length(g, fq, beta, "higher")["alpha"]
+                    fs = g + a * beta * (fq - g)
+                    dH = float(np.sum(fs * np.log(fs / w)) - np.sum(g * np.log(g / w)))
+                    x = fq / g - 1
+                    xh = a * beta * x
+                    kept = float(np.sum(g * (1 + xh) * np.log1p(xh)) - a * beta * np.sum(g * x * np.log1p(x)))
+                    assert kept <= 1e-15
+                    assert dH <= 1e-15
+                    term = dH - kept
+                    if eps > 1e-2 and tau1 > 1e-3:
+                        assert term * (1 if Pr < 1 else -1) > 0
+
+
+def test_esbgk_lattice_conserves():
+    rho, u = W.taylor_green_2d(16, u0=0.08)
+    f = oracle.init_equilibrium(rho, u)
+    c, _ = oracle.lattice(2)
+    for Pr in (0.71, 2.0):
+        out, alpha, (ng, nd, nf) = oracle.step_esbgk(f, 30, 0.01, Pr, want_alpha=True)
+        assert nf == 0 and np.all(out > 0)
+        assert abs(out.sum() - f.sum()) < 1e-12 * f.sum()
+        for a in range(2):
+            m0 = np.tensordot(c[:, a], f, axes=(0, 0)).sum()
+            m1 = np.tensordot(c[:, a], out, axes=(0, 0)).sum()
+            assert abs(m1 - m0) < 1e-13
