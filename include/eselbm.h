@@ -122,8 +122,12 @@ typedef enum {
  *             sums (cells with all |x_i| below 0.02 in single precision and
  *             0.005 in double are evaluated through truncated power series
  *             of the same sums, accurate to the rounding of the type).
- *   n_newton  ELBM and ITERATE1 modes: Newton iterations summed over cells.
- *   n_mirror_fallback  ELBM and ITERATE1 modes: cells that kept alpha_Lower.
+ *   n_newton  ELBM and ITERATE1 modes: Newton iterations summed over cells;
+ *             with ES-BGK on (eselbm_set_prandtl), the quasi-equilibrium's
+ *             Newton iterations.
+ *   n_mirror_fallback  ELBM and ITERATE1 modes: cells that kept alpha_Lower;
+ *             with ES-BGK on, cells whose quasi-equilibrium did not converge
+ *             and that collided with the equilibrium instead.
  */
 typedef struct {
     double mass, mom[3], kinetic, H;
@@ -179,6 +183,23 @@ eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut);
  * dissipation loss (periodic differences) reject a walled grid
  * (ESELBM_E_UNSUPPORTED).  The table is copied to the device synchronously. */
 eselbm_status eselbm_set_walls(eselbm_handle h, int walls, const double *velocity);
+
+/* Entropic lattice ES-BGK collision (the paper's section on the exact path
+ * length of the entropic lattice ES-BGK model).  prandtl: the Prandtl
+ * number Pr > 0; 1 (the default) is the ordinary step.  With Pr != 1 the
+ * collision relaxes towards the quasi-equilibrium f^QE instead of f^eq:
+ * the minimiser of H with the cell's mass and momentum and the pressure
+ * tensor P(f^eq) + c_Pr (P(g) - P(f^eq)), P(f) = sum_i f_i c_i c_i,
+ * c_Pr = (1 - 1/Pr) / (1 + 1/(2 tau1 Pr)), tau1 being eselbm_step's tau.
+ * f^QE = f^eq exp(delta . (1, c, c c)) with delta found by Newton's method
+ * per cell.  The path length keeps its closed form with x = f^QE / g - 1,
+ * and the shear viscosity becomes nu = tau1 Pr / 3.  Where the Newton
+ * iteration does not converge (a target pressure that no positive state
+ * carries) the cell collides with f^eq and is counted in
+ * n_mirror_fallback.  Modes HIGHER, LOWER and BGK only; no force, no walls,
+ * no adjoint (eselbm_step and eselbm_adjoint_step return
+ * ESELBM_E_UNSUPPORTED).  Error: ESELBM_E_ARG unless Pr is finite and > 0. */
+eselbm_status eselbm_set_prandtl(eselbm_handle h, double prandtl);
 
 /* Registers a body-force density F (device float, [D][nz][ny][nx]) added
  * after the collision as f* += feq(rho, u + F/rho) - feq(rho, u) (exact

@@ -27,6 +27,7 @@ struct eselbm_ctx {
     DevStats *dev_stats;   // kStatSlots slots, then the wall table
     int walls;             // bit a: axis a bounded by diffuse walls
     double *wall_eq;       // device [2 D][Q], inside the dev_stats allocation
+    double prandtl;        // ES-BGK Prandtl number; 1: the equilibrium itself
 };
 
 static thread_local std::string g_err;
@@ -67,6 +68,7 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
     h->g = Grid{lattice == ESELBM_D2Q9 ? 2 : 3, Q, nx, ny, nz, N};
     h->dtype = dtype;
     h->mode = ESELBM_MODE_HIGHER;
+    h->prandtl = 1.0;
     hipError_t e = hipGetDevice(&h->device);
     if (e != hipSuccess) {
         delete h;
@@ -117,6 +119,14 @@ eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut)
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_set_nut_field: NULL handle");
     h->nut_field = nut;
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_set_prandtl(eselbm_handle h, double prandtl)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_prandtl: NULL handle");
+    if (!(prandtl > 0.0) || !std::isfinite(prandtl)) return fail(ESELBM_E_ARG, "eselbm_set_prandtl: Pr must be finite and > 0");
+    h->prandtl = prandtl;
     return ESELBM_OK;
 }
 
@@ -185,6 +195,13 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
     if (nsteps < 1) return fail(ESELBM_E_ARG, "eselbm_step: nsteps must be >= 1");
     if (h->force && h->mode == ESELBM_MODE_LBGK) return fail(ESELBM_E_UNSUPPORTED, "eselbm_step: forcing in the classic LBGK mode");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_step: tau must be finite and > 0");
+    // ES-BGK: c_Pr = (1 - 1/Pr) / (1 + 1/(2 tau1 Pr)), tau1 = tau
+    const double cpr = h->prandtl == 1.0 ? 0.0 : (1.0 - 1.0 / h->prandtl) / (1.0 + 1.0 / (2.0 * tau * h->prandtl));
+    if (cpr != 0.0) {
+        if (h->mode != ESELBM_MODE_HIGHER && h->mode != ESELBM_MODE_LOWER && h->mode != ESELBM_MODE_BGK)
+            return fail(ESELBM_E_UNSUPPORTED, "eselbm_step: ES-BGK takes the modes HIGHER, LOWER and BGK");
+        if (h->force || h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_step: ES-BGK is periodic and unforced");
+    }
     const size_t bytes = (size_t)h->g.Q * (size_t)h->g.N * elem_size(h->dtype);
     const char *a = (const char *)f_in, *b = (const char *)f_out;
     if (a < b + bytes && b < a + bytes) return fail(ESELBM_E_ARG, "eselbm_step: f_in and f_out overlap");
@@ -206,6 +223,7 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
         sa.alpha_out = last ? h->alpha_field : nullptr;
         sa.nut_out = last ? h->nut_field : nullptr;
         sa.stats = (last && h->stats_on) ? h->dev_stats : nullptr;
+        sa.cpr = cpr;
         const bool diag = sa.alpha_out != nullptr || sa.nut_out != nullptr || sa.stats != nullptr;
         if (sa.stats) {
             hipError_t e = launch_reset_stats(h->dev_stats, s);
@@ -293,6 +311,7 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
     if (h->mode == ESELBM_MODE_ELBM || h->mode == ESELBM_MODE_ITERATE1 || h->mode == ESELBM_MODE_LBGK)
         return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the ELBM, Iterate1 and classic LBGK modes");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: the adjoint is periodic only");
+    if (h->prandtl != 1.0) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the ES-BGK collision");
     AdjArgs a;
     a.fn = f_n;
     a.lam_next = lam_next;

@@ -36,6 +36,7 @@ struct StepArgs {
     void *alpha_out;     // [N] compute type or null
     void *nut_out;       // [N] compute type or null: nu_T of Eq. nuT
     DevStats *stats;     // kStatSlots slots or null
+    double cpr;          // ES-BGK stress factor c_Pr; 0: the equilibrium itself
 };
 
 // Launchers (return the hipError_t of the launch).

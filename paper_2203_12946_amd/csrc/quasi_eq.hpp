@@ -1,0 +1,212 @@
+// Quasi-equilibrium of the entropic lattice ES-BGK collision (the section on
+// the exact path length of the entropic lattice ES-BGK model).
+//
+// f^QE minimises H over the states with the cell's mass and momentum and the
+// pressure tensor P(f^eq) + c_Pr sigma, sigma = P(g) - P(f^eq), P(f) =
+// sum_i f_i c_i c_i, c_Pr = (1 - 1/Pr) / (1 + 1/(2 tau1 Pr)).  The paper
+// writes the Maxwellian pressure where P(f^eq) stands: the lattice's own
+// equilibrium pressure takes its place, so that f^QE = f^eq at Pr = 1 or
+// sigma = 0.  The minimiser is f^QE_i = f^eq_i exp(delta . phi_i) over the
+// basis phi = (1, c_a, c_a c_b for a <= b) (f^eq is the minimiser without
+// the pressure constraint); delta solves the moment equations
+//   F_k(delta) = sum_i f^eq_i expm1(delta . phi_i) phi_ik - T_k = 0,
+// T = (0, 0, c_Pr sigma), and is found numerically, as the paper does, by
+// Newton's method from delta = 0.
+//
+// Structure for a lane:
+//  - On the tensor-product lattice every product phi_k phi_l reduces to a
+//    monomial c_x^ex c_y^ey c_z^ez with exponents in {0, 1, 2} (c^3 = c,
+//    c^4 = c^2).  All Q such moments of a per-population value are taken by
+//    contracting one axis at a time (three adds per row of three), so the
+//    residual and the Jacobian sum_i f^QE_i phi_i phi_i^T come from two
+//    contractions per iteration instead of K^2 sums.
+//  - The Jacobian is factored in single precision whatever the arithmetic
+//    type: Newton then converges at least linearly at the rate of that
+//    rounding (about 1e-7 times its condition), a handful of iterations
+//    to double precision, while the residual, the step and delta are in E.
+#pragma once
+
+#include "lattice.hpp"
+
+namespace eselbm {
+
+__device__ inline float expm1_(float v) { return expm1f(v); }
+__device__ inline double expm1_(double v) { return expm1(v); }
+
+template <int D>
+struct QEBasis {
+    static constexpr int K = D == 2 ? 6 : 10;
+    // exponent of basis function k along axis a: 1, c_x, c_y[, c_z], then
+    // c_a c_b for a <= b in the order xx, xy[, xz], yy[, yz, zz]
+    __host__ __device__ static constexpr int e(int k, int a)
+    {
+        if (k == 0) return 0;
+        if (k <= D) return a == k - 1 ? 1 : 0;
+        int q = k - 1 - D;
+        for (int p = 0; p < D; ++p)
+            for (int r = p; r < D; ++r) {
+                if (q == 0) return (a == p) + (a == r);
+                --q;
+            }
+        return 0;
+    }
+    // reduced exponent of a product: c^3 = c, c^4 = c^2
+    __host__ __device__ static constexpr int red(int n) { return n == 0 ? 0 : (n % 2 == 1 ? 1 : 2); }
+    // moment index (ex + 3 ey + 9 ez) of basis function k, and of phi_k phi_l
+    __host__ __device__ static constexpr int m1(int k) { return e(k, 0) + 3 * e(k, 1) + 9 * e(k, 2); }
+    __host__ __device__ static constexpr int m2(int k, int l)
+    {
+        return red(e(k, 0) + e(l, 0)) + 3 * red(e(k, 1) + e(l, 1)) + 9 * red(e(k, 2) + e(l, 2));
+    }
+    // phi_k at population i
+    __host__ __device__ static constexpr int phi(int k, int i)
+    {
+        int v = 1;
+        for (int a = 0; a < D; ++a) {
+            const int c = Lat<D>::c(i, a);
+            v *= e(k, a) == 0 ? 1 : (e(k, a) == 1 ? c : c * c);
+        }
+        return v;
+    }
+};
+
+// Moments m[ex + 3 ey + 9 ez] = sum_i v_i c_x^ex c_y^ey c_z^ez, exponents in
+// {0, 1, 2}: per axis, a row (v_-, v_0, v_+) becomes (sum, v_+ - v_-, v_+ + v_-).
+template <int D, typename V>
+__device__ inline void contract_rows(V (&m)[Lat<D>::Q])
+{
+    constexpr int Q = Lat<D>::Q;
+#pragma unroll
+    for (int stride = 1; stride < Q; stride *= 3) {
+#pragma unroll
+        for (int base = 0; base < Q; ++base) {
+            if ((base / stride) % 3 != 0) continue;
+            const V a = m[base], b = m[base + stride], c = m[base + 2 * stride];
+            m[base] = (a + b) + c;
+            m[base + stride] = c - a;
+            m[base + 2 * stride] = c + a;
+        }
+    }
+}
+
+// delta . phi_i, with phi_i's entries compile-time after unrolling
+template <int D, typename E>
+__device__ inline E qe_arg(int i, const E (&delta)[QEBasis<D>::K])
+{
+    E s = E(0);
+#pragma unroll
+    for (int k = 0; k < QEBasis<D>::K; ++k) {
+        const int ph = QEBasis<D>::phi(k, i);
+        if (ph == 1) s += delta[k];
+        else if (ph == -1) s -= delta[k];
+    }
+    return s;
+}
+
+template <typename E>
+struct QECfg;
+template <>
+struct QECfg<float> {
+    static constexpr float tol = 1e-6f;  // max |Newton step| at which it stops
+    static constexpr int maxit = 12;
+};
+template <>
+struct QECfg<double> {
+    static constexpr double tol = 1e-13;
+    static constexpr int maxit = 16;
+};
+
+// Replaces d = feq - g by f^QE - g.  p holds the stored values (g, or g - w
+// when SH), d the deviation of the equilibrium; E is the arithmetic type of
+// the solve.  Returns false when Newton does not converge (the target
+// pressure lies beyond what positive populations carry): d is then left
+// as the equilibrium's.  iters receives the Newton iterations.
+template <int D, typename T, typename E, bool SH>
+__device__ inline bool quasi_equilibrium(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>::Q], E cpr, int &iters)
+{
+    using B = QEBasis<D>;
+    constexpr int Q = Lat<D>::Q, K = B::K;
+    auto fe = [&](int i) { return E(gval<D, T, SH>(i, p)) + E(d[i]); };
+    // target T_k = c_Pr sigma_k = -c_Pr sum_i d_i phi_ik (second moments)
+    E tgt[K];
+    {
+        E md[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) md[i] = E(d[i]);
+        contract_rows<D, E>(md);
+#pragma unroll
+        for (int k = 0; k < K; ++k) tgt[k] = k <= D ? E(0) : -cpr * md[B::m1(k)];
+    }
+    // moments of f^eq (single precision: they serve the Jacobian only)
+    float mfe[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) mfe[i] = float(fe(i));
+    contract_rows<D, float>(mfe);
+
+    E delta[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) delta[k] = E(0);
+    bool conv = false;
+    int it = 0;
+    for (; it < QECfg<E>::maxit && !conv; ++it) {
+        // r_i = feq_i expm1(delta . phi_i): its moments give the residual,
+        // and with those of feq the Jacobian's (f^QE = feq + r)
+        E mr[Q];
+#pragma unroll
+        for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_(qe_arg<D, E>(i, delta));
+        contract_rows<D, E>(mr);
+        // Cholesky of J_kl = sum f^QE phi_k phi_l, packed lower triangle
+        float L[K * (K + 1) / 2];
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+#pragma unroll
+            for (int l = 0; l <= k; ++l) L[k * (k + 1) / 2 + l] = mfe[B::m2(k, l)] + float(mr[B::m2(k, l)]);
+        bool spd = true;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            float dj = L[j * (j + 1) / 2 + j];
+#pragma unroll
+            for (int q = 0; q < j; ++q) dj -= L[j * (j + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+            spd = spd && dj > 0.0f;
+            const float ljj = sqrt_(fmax_(dj, 1e-30f)), ij = rcp_(ljj);
+            L[j * (j + 1) / 2 + j] = ljj;
+#pragma unroll
+            for (int r = j + 1; r < K; ++r) {
+                float v = L[r * (r + 1) / 2 + j];
+#pragma unroll
+                for (int q = 0; q < j; ++q) v -= L[r * (r + 1) / 2 + q] * L[j * (j + 1) / 2 + q];
+                L[r * (r + 1) / 2 + j] = v * ij;
+            }
+        }
+        // step s = -J^-1 F in E
+        E y[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            E v = tgt[k] - mr[B::m1(k)];
+#pragma unroll
+            for (int q = 0; q < k; ++q) v -= E(L[k * (k + 1) / 2 + q]) * y[q];
+            y[k] = v * E(rcp_(L[k * (k + 1) / 2 + k]));
+        }
+        E mx = E(0);
+#pragma unroll
+        for (int k = K - 1; k >= 0; --k) {
+            E v = y[k];
+#pragma unroll
+            for (int q = k + 1; q < K; ++q) v -= E(L[q * (q + 1) / 2 + k]) * y[q];
+            y[k] = v * E(rcp_(L[k * (k + 1) / 2 + k]));
+            delta[k] += y[k];
+            mx = fmax_(mx, abs_(y[k]));
+        }
+        // a NaN step fails both comparisons and ends the loop unconverged
+        if (!spd || !(mx < E(1))) break;
+        conv = mx <= E(QECfg<E>::tol);
+    }
+    iters = it;
+    if (!conv) return false;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_(qe_arg<D, E>(i, delta)));
+    conserve_moments<D, T>(d);
+    return true;
+}
+
+}  // namespace eselbm

@@ -12,6 +12,7 @@
 
 #include "internal.hpp"
 #include "lattice.hpp"
+#include "quasi_eq.hpp"
 
 #include <type_traits>
 
@@ -195,6 +196,15 @@ __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)
 template <typename S, int MODE>
 constexpr int step_waves() { return is_mirror_mode(MODE) ? 2 : StepPolicy<S>::waves; }
 
+// The ES-BGK quasi-equilibrium solve holds a K x K factor, its moments and
+// the Newton state besides the two Q-arrays: two waves per SIMD for D2Q9 in
+// single precision, one for D3Q27 (K = 10) or where the solve runs in double.
+template <int D, typename S, int MODE, bool QE>
+constexpr int step_waves_qe()
+{
+    return QE ? ((StepPolicy<S>::eq_f64 || D == 3) ? 1 : 2) : step_waves<S, MODE>();
+}
+
 // Pull with diffuse walls (the boundary rule of the lid-driven cavity,
 // Sec. V C; the paper cites Ansumali and Karlin for it): on an axis whose
 // bit is set in walls the domain is bounded by walls half-way outside the
@@ -269,8 +279,8 @@ __device__ inline void pull_walls(const StepArgs &a, int x, int y, int z, typena
     }
 }
 
-template <int D, typename S, int MODE, bool DIAG, bool FORCE, bool WALL = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves<S, MODE>()))) void k_step(StepArgs a)
+template <int D, typename S, int MODE, bool DIAG, bool FORCE, bool WALL = false, bool QE = false>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_qe<D, S, MODE, QE>()))) void k_step(StepArgs a)
 {
     using T = typename Storage<S>::T;
     using Pol = StepPolicy<S>;
@@ -350,7 +360,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves<
             // accumulates over steps.  The path length stays in T.
             using EQ = typename std::conditional<Pol::eq_f64, double, T>::type;
             form_deviation<D, T, EQ, MODE == MODE_LBGK>(dev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
+            // ES-BGK: the quasi-equilibrium replaces the equilibrium, and the
+            // path length is found from x = f^QE / g - 1 as before
+            int qe_it = 0;
+            bool qe_ok = true;
+            if constexpr (QE) qe_ok = quasi_equilibrium<D, T, EQ, SH>(p, dd, EQ(a.cpr), qe_it);
             alpha = path_length<D, T, typename Pol::Exact, MODE, SH>(p, dd, a.beta, info);
+            if constexpr (QE) {
+                info.iters = qe_it;
+                info.fallback = !qe_ok;
+            }
             if (Pol::ab_split) {
                 const double abE = double(alpha) * a.beta;
                 ab = T(abE);
@@ -425,6 +444,16 @@ static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
     if (a.g.ny > 65535 || a.g.nz > 65535) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)((a.g.nx + bx - 1) / bx), (unsigned)a.g.ny, (unsigned)a.g.nz), block(bx);
     const bool force = a.force != nullptr;
+    if (a.cpr != 0.0) {
+        // ES-BGK: periodic, unforced, path lengths alpha_Higher, alpha_Lower, 2
+        if constexpr (MODE == MODE_HIGHER || MODE == MODE_LOWER || MODE == MODE_BGK) {
+            if (force || a.walls) return hipErrorInvalidValue;
+            if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, false, false, true>), grid, block, 0, s, a);
+            else hipLaunchKernelGGL((k_step<D, S, MODE, false, false, false, true>), grid, block, 0, s, a);
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.walls) {
         if (force) return hipErrorInvalidValue;
         if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, false, true>), grid, block, 0, s, a);

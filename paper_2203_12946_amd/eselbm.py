@@ -61,6 +61,7 @@ _SIGNATURES = {
     "eselbm_set_nut_field": [_vp, _vp],
     "eselbm_set_force": [_vp, _vp],
     "eselbm_set_walls": [_vp, ctypes.c_int, _vp],
+    "eselbm_set_prandtl": [_vp, ctypes.c_double],
     "eselbm_init_equilibrium": [_vp, _vp, _vp, _vp, _vp],
     "eselbm_step": [_vp, _vp, _vp, ctypes.c_int, ctypes.c_double, _vp],
     "eselbm_alpha_stats": [_vp, ctypes.POINTER(Stats), ctypes.c_int, _vp],
@@ -185,6 +186,10 @@ class Solver:
             for k, comp in enumerate(v):
                 uw[(2 * a + sd) * 3 + k] = float(comp)
         _check(lib.eselbm_set_walls(self._h, mask, ctypes.cast(uw, _vp)))
+
+    def set_prandtl(self, prandtl: float):
+        """Entropic ES-BGK collision at Prandtl number ``prandtl`` (1: off)."""
+        _check(lib.eselbm_set_prandtl(self._h, float(prandtl)))
 
     def set_force(self, F: torch.Tensor | None):
         """Register a [D, *shape] float32 body-force density (F32 storage only)."""

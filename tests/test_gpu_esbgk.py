@@ -1,0 +1,197 @@
+"""Entropic lattice ES-BGK on the GPU (the quasi-equilibrium collision with
+the closed-form path length, the paper's section on the ES-BGK model),
+through the C ABI, versus the FP64 oracle.
+
+Tolerances: FP64 alpha within 1e-9 per cell and the state within 1e-12 of
+its scale after one step, rho and u within 1e-11 after 200 steps, the
+quasi-equilibrium fallback in exactly the oracle's cells; single precision
+alpha within 1e-5 and the state within 1e-5 of its scale after one step
+(the quasi-equilibrium's Newton solve runs in the equilibrium's precision),
+and within 4x the storage-rounding-only error after 200 steps.  Cells where
+the two sides take different branches (the gate, or a quasi-equilibrium
+that converges on one side only, its target pressure at the edge of what
+positive populations carry) are counted and bounded."""
+import math
+import sys
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2203_12946_amd import workloads as W
+from tests._states import mixed_mirror_lattice
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def es():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2203_12946_amd import eselbm
+    return eselbm
+
+
+def _log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _rounded(f, dtype):
+    if dtype == "f64":
+        return f
+    if dtype == "f32":
+        return f.astype(np.float32).astype(np.float64)
+    D = f.ndim - 1
+    _, w = oracle.lattice(D)
+    w = w.reshape((-1,) + (1,) * D)
+    return w + (f - w).astype(np.float32).astype(np.float64)
+
+
+def _upload(s, f, dtype):
+    if dtype == "f32s":
+        D = f.ndim - 1
+        _, w = oracle.lattice(D)
+        f = f - w.reshape((-1,) + (1,) * D)
+    return torch.from_numpy(np.ascontiguousarray(f)).to(s.storage_dtype).cuda()
+
+
+def _download(t, dtype, D):
+    got = t.double().cpu().numpy()
+    if dtype == "f32s":
+        _, w = oracle.lattice(D)
+        got = got + w.reshape((-1,) + (1,) * D)
+    return got
+
+
+@pytest.mark.parametrize("mode", ["higher", "lower", "bgk"])
+@pytest.mark.parametrize("D,shape,seed", [(2, (24, 40), 5), (3, (8, 10, 12), 6)])
+@pytest.mark.parametrize("Pr,tau1", [(0.71, 0.01), (2.0, 0.3), (0.3, 0.3)])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
+def test_esbgk_one_step(es, D, shape, seed, mode, Pr, tau1, dtype):
+    """Gated, series-range, exact-range and far-from-equilibrium cells in
+    one lattice (at Pr = 0.3, tau1 = 0.3 some quasi-equilibria do not exist
+    and fall back to the equilibrium)."""
+    lat = "D2Q9" if D == 2 else "D3Q27"
+    f0 = _rounded(mixed_mirror_lattice(D, shape, seed), dtype)
+    ref, ra, (ng, nd, nfall) = oracle.step_esbgk(f0, 1, tau1, Pr, mode=mode, want_alpha=True)
+    s = es.Solver(lat, shape, dtype=dtype, mode=mode)
+    s.set_prandtl(Pr)
+    alpha = torch.empty(shape, dtype=s.compute_dtype, device="cuda")
+    s.set_alpha_field(alpha)
+    s.set_stats(True)
+    out = s.empty_state()
+    s.step(_upload(s, f0, dtype), out, 1, tau1)
+    st = s.stats()
+    torch.cuda.synchronize()
+    ga = alpha.double().cpu().numpy()
+    got = _download(out, dtype, D)
+    tol_a = 1e-9 if dtype == "f64" else 1e-5
+    bad = np.abs(ga - ra) > tol_a
+    err = np.abs(got - ref).max(axis=0)
+    scale = np.max(np.abs(ref))
+    tol_f = 1e-12 if dtype == "f64" else 1e-5
+    bad |= err > tol_f * scale
+    nbad = int(bad.sum())
+    da = float(np.max(np.abs(ga - ra)[~bad])) if (~bad).any() else 0.0
+    df = float(np.max(err[~bad])) / scale if (~bad).any() else 0.0
+    _log(f"[esbgk {lat} {dtype} {mode} Pr={Pr} tau1={tau1}] max|dalpha|={da:.2e} max|df|/scale={df:.2e}, "
+         f"branch differences {nbad}, gated {st['n_gated']}/{ng}, guard {st['n_guard']}/{nd}, "
+         f"QE fallback {st['n_mirror_fallback']}/{nfall}, QE Newton {st['n_newton']}")
+    if dtype == "f64":
+        assert nbad == 0
+        assert st["n_mirror_fallback"] == nfall and st["n_gated"] == ng
+    else:
+        assert nbad <= max(2, nfall // 4)
+        assert abs(st["n_mirror_fallback"] - nfall) <= nbad
+    assert st["n_nonpos"] == 0
+    assert st["n_newton"] >= st["n_cells"] - st["n_mirror_fallback"]
+
+
+@pytest.mark.parametrize("Pr", [0.71, 2.0])
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f32s"])
+def test_esbgk_rollout(es, Pr, dtype):
+    """200 steps of a 2-D Taylor-Green vortex (u0 = 0.1) with alpha_Higher."""
+    n, steps, tau1 = 48, 200, 0.02
+    rho, u = W.taylor_green_2d(n, u0=0.1)
+    f0 = oracle.init_equilibrium(rho, u)
+    ref = oracle.step_esbgk(f0, steps, tau1, Pr)
+    rr, ru = oracle.moments(ref)
+    s = es.Solver("D2Q9", (n, n), dtype=dtype)
+    s.set_prandtl(Pr)
+    a = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    b = s.empty_state()
+    s.step(a, b, steps, tau1)
+    gr, gu = s.moments(b)
+    torch.cuda.synchronize()
+    drho = float(np.max(np.abs(gr.cpu().numpy() - rr)))
+    du = float(np.linalg.norm(gu.cpu().numpy() - ru) / np.linalg.norm(ru))
+    if dtype == "f64":
+        _log(f"[esbgk rollout {dtype} Pr={Pr}] drho={drho:.2e} du={du:.2e}")
+        assert drho <= 1e-11 and du <= 1e-11
+    else:
+        f = _rounded(f0, dtype)
+        for _ in range(steps):
+            f = _rounded(oracle.step_esbgk(f, 1, tau1, Pr), dtype)
+        er, eu = oracle.moments(f)
+        fr = float(np.max(np.abs(er - rr)))
+        fu = float(np.linalg.norm(eu - ru) / np.linalg.norm(ru))
+        _log(f"[esbgk rollout {dtype} Pr={Pr}] drho={drho:.2e} du={du:.2e} | storage-rounding-only {fr:.2e} {fu:.2e}")
+        assert drho <= 4 * fr and du <= 4 * fu
+
+
+@pytest.mark.parametrize("Pr", [0.5, 0.71, 2.0])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_esbgk_viscosity_on_gpu(es, Pr, dtype):
+    """nu = tau1 theta Pr: a 2-D Taylor-Green vortex decays at 4 nu k^2."""
+    n, tau1 = 32, 0.05
+    rho, u = W.taylor_green_2d(n, u0=0.02)
+    k = 2 * math.pi / n
+    s = es.Solver("D2Q9", (n, n), dtype=dtype)
+    s.set_prandtl(Pr)
+    a = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    b = s.empty_state()
+    s.set_stats(True)
+    s.step(a, b, 100, tau1)
+    e0 = s.stats()["kinetic"]
+    s.step(b, a, 200, tau1)
+    st = s.stats()
+    nu = -math.log(st["kinetic"] / e0) / 200 / (4 * k * k)
+    _log(f"[esbgk viscosity {dtype} Pr={Pr}] nu {nu:.6f} against tau1 Pr / 3 = {tau1 * Pr / 3:.6f}")
+    assert abs(nu / (tau1 * Pr / 3.0) - 1) < 2e-3
+    assert st["n_mirror_fallback"] == 0
+
+
+def test_esbgk_pr_one_is_the_plain_step(es):
+    n = 32
+    rho, u = W.taylor_green_2d(n, u0=0.08)
+    outs = []
+    for pr in (None, 1.0):
+        s = es.Solver("D2Q9", (n, n), dtype="f32")
+        if pr is not None:
+            s.set_prandtl(pr)
+        a = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+        b = s.empty_state()
+        s.step(a, b, 10, 0.02)
+        outs.append(b.cpu())
+    assert torch.equal(outs[0], outs[1])
+
+
+def test_esbgk_rejections(es):
+    s = es.Solver("D2Q9", (8, 8), dtype="f32")
+    a, b = s.empty_state(), s.empty_state()
+    with pytest.raises(es.EselbmError):
+        s.set_prandtl(0.0)
+    s.set_prandtl(0.71)
+    for mode in ("elbm", "iterate1", "lbgk"):
+        s.set_mode(mode)
+        with pytest.raises(es.EselbmError):
+            s.step(a, b, 1, 0.1)
+    s.set_mode("higher")
+    s.set_walls([True, True])
+    with pytest.raises(es.EselbmError):
+        s.step(a, b, 1, 0.1)
+    s.set_walls(None)
+    lam, lam2 = s.empty_adjoint(), s.empty_adjoint()
+    with pytest.raises(es.EselbmError):
+        s.adjoint_step(a, lam, lam2, 0.1)
