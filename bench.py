@@ -32,7 +32,7 @@ sys.path.insert(0, str(ROOT))
 HBM_PEAK_GBS = 8000.0
 METRIC = "ESELBM MLUPS & % HBM roofline (D3Q27 FP32 vs FP64); adjoint/forward time"
 KERNEL_SOURCES = ["paper_2203_12946_amd/csrc/step_kernel.hpp", "paper_2203_12946_amd/csrc/step_f32.hip",
-                  "paper_2203_12946_amd/csrc/lattice.hpp"]
+                  "paper_2203_12946_amd/csrc/lattice.hpp", "paper_2203_12946_amd/csrc/quasi_eq.hpp"]
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_d3q27_f32_256.md"
 
 
@@ -63,8 +63,10 @@ def traffic_bytes():
     return int(kv["bytes_per_launch"])
 
 
-def time_forward(es, torch, W, wl, dtype: str, mode: str, steps: int, warmup: int, rho_d, u_d):
+def time_forward(es, torch, W, wl, dtype: str, mode: str, steps: int, warmup: int, rho_d, u_d,
+                 prandtl: float = 1.0):
     s = es.Solver(wl.lattice, wl.shape, dtype=dtype, mode=mode)
+    s.set_prandtl(prandtl)
     a = s.init_equilibrium(rho_d, u_d)
     b = s.empty_state()
     stream = torch.cuda.current_stream()
@@ -268,6 +270,19 @@ def main():
                     newton_per_ungated_cell=round(r["stats"]["n_newton"] / ung, 3),
                     n_mirror_fallback=r["stats"]["n_mirror_fallback"])
             _log(f"bench: {dtype} {mode} {r['mlups']:.0f} MLUPS")
+        # entropic ES-BGK (quasi-equilibrium solved per cell) at Pr = 0.71
+        for dtype, bpc in (("f32", 216), ("f64", 432)):
+            _log(f"bench: {dtype} higher ES-BGK")
+            r = time_forward(es, torch, W, wl, dtype, "higher", max(20, args.steps // 4), 5, rho_d, u_d,
+                             prandtl=0.71)
+            gbs = bpc * cells / (r["kernel_ms"] * 1e-3) / 1e9
+            variants[f"{dtype}_higher_esbgk_pr0.71"] = dict(
+                mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 4),
+                hbm_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_cell=bpc,
+                n_gated=r["stats"]["n_gated"], n_exact=r["stats"]["n_exact"],
+                qe_newton_per_cell=round(r["stats"]["n_newton"] / max(1, r["stats"]["n_cells"]), 3),
+                n_qe_fallback=r["stats"]["n_mirror_fallback"])
+            _log(f"bench: {dtype} ES-BGK {r['mlups']:.0f} MLUPS")
     del rho_d, u_d
     torch.cuda.empty_cache()
 
