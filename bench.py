@@ -194,7 +194,7 @@ def cpu_baseline(W, wl, seconds_target: float = 15.0):
         t0 = time.perf_counter()
         oracle.step(f0, 1, wl.tau)
         per_step = time.perf_counter() - t0
-        nsteps = max(1, min(20, int(budget / max(per_step, 1e-3))))
+        nsteps = max(1, min(1000, int(budget / max(per_step, 1e-3))))
         t0 = time.perf_counter()
         oracle.step(f0, nsteps, wl.tau)
         dt = time.perf_counter() - t0
