@@ -205,6 +205,16 @@ constexpr int step_waves_qe()
     return QE ? ((StepPolicy<S>::eq_f64 || D == 3) ? 1 : 2) : step_waves<S, MODE>();
 }
 
+// The walled pull keeps its per-population wall decisions and the wall
+// node's mass balance live beside the two Q-arrays: two waves per SIMD for
+// D2Q9 in single precision, one for D3Q27 or in double, which removes the
+// spills the periodic step's occupancy floor would force on it.
+template <int D, typename S, int MODE, bool WALL, bool QE>
+constexpr int step_waves_k()
+{
+    return WALL ? ((D == 3 || StepPolicy<S>::eq_f64) ? 1 : 2) : step_waves_qe<D, S, MODE, QE>();
+}
+
 // Pull with diffuse walls (the boundary rule of the lid-driven cavity,
 // Sec. V C; the paper cites Ansumali and Karlin for it): on an axis whose
 // bit is set in walls the domain is bounded by walls half-way outside the
@@ -280,7 +290,7 @@ __device__ inline void pull_walls(const StepArgs &a, int x, int y, int z, typena
 }
 
 template <int D, typename S, int MODE, bool DIAG, bool FORCE, bool WALL = false, bool QE = false>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_qe<D, S, MODE, QE>()))) void k_step(StepArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_k<D, S, MODE, WALL, QE>()))) void k_step(StepArgs a)
 {
     using T = typename Storage<S>::T;
     using Pol = StepPolicy<S>;
