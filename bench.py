@@ -64,22 +64,28 @@ def traffic_bytes():
 
 
 def time_forward(es, torch, W, wl, dtype: str, mode: str, steps: int, warmup: int, rho_d, u_d,
-                 prandtl: float = 1.0):
+                 prandtl: float = 1.0, in_place: bool = False):
     s = es.Solver(wl.lattice, wl.shape, dtype=dtype, mode=mode)
     s.set_prandtl(prandtl)
     a = s.init_equilibrium(rho_d, u_d)
     b = s.empty_state()
     stream = torch.cuda.current_stream()
-    for _ in range(warmup):
-        s.step(a, b, 1, wl.tau)
+    if in_place:
+        # one lattice: steps in pairs (the AA pattern's two halves)
+        del b
+        b = a
+        steps += steps % 2
+    per = 2 if in_place else 1
+    for _ in range(0, warmup, per):
+        s.step(a, b, per, wl.tau)
         a, b = b, a
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
     ev0.record(stream)
-    for _ in range(steps):
-        s.step(a, b, 1, wl.tau)
+    for _ in range(0, steps, per):
+        s.step(a, b, per, wl.tau)
         a, b = b, a
     ev1.record(stream)
     torch.cuda.synchronize()
@@ -88,7 +94,7 @@ def time_forward(es, torch, W, wl, dtype: str, mode: str, steps: int, warmup: in
     wall_s = t1 - t0
     # diagnostics step outside the timed region: conservation and branch counts
     s.set_stats(True)
-    s.step(a, b, 1, wl.tau)
+    s.step(a, b, per, wl.tau)
     st = s.stats()
     cells = s.cells
     del a, b, s
@@ -270,6 +276,17 @@ def main():
                     newton_per_ungated_cell=round(r["stats"]["n_newton"] / ung, 3),
                     n_mirror_fallback=r["stats"]["n_mirror_fallback"])
             _log(f"bench: {dtype} {mode} {r['mlups']:.0f} MLUPS")
+        # in place on one lattice (the AA pattern)
+        for dtype, bpc in (("f32", 216), ("f64", 432)):
+            _log(f"bench: {dtype} higher in place")
+            r = time_forward(es, torch, W, wl, dtype, "higher", max(20, args.steps // 2), 6, rho_d, u_d,
+                             in_place=True)
+            gbs = bpc * cells / (r["kernel_ms"] * 1e-3) / 1e9
+            variants[f"{dtype}_higher_in_place"] = dict(
+                mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 4),
+                hbm_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_cell=bpc,
+                n_gated=r["stats"]["n_gated"], n_exact=r["stats"]["n_exact"])
+            _log(f"bench: {dtype} in place {r['mlups']:.0f} MLUPS")
         # entropic ES-BGK (quasi-equilibrium solved per cell) at Pr = 0.71
         for dtype, bpc in (("f32", 216), ("f64", 432)):
             _log(f"bench: {dtype} higher ES-BGK")

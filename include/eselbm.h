@@ -216,7 +216,15 @@ eselbm_status eselbm_init_equilibrium(eselbm_handle h, const double *rho, const 
 /* Runs nsteps >= 1 pull-stream + collide steps.
  * f_in holds the initial state; the result is in f_out.  For nsteps > 1,
  * f_in is the ping-pong partner and is overwritten.  f_in and f_out must
- * be distinct, non-overlapping buffers of Q * n_cells storage elements.
+ * be distinct, non-overlapping buffers of Q * n_cells storage elements, or
+ * the same buffer: then the steps run in place on that one lattice (the
+ * AA pattern: odd steps pull from the neighbours and write each population
+ * back into the slot of the opposite direction it came from, even steps
+ * read and write the cell's own slots), which halves the state memory and
+ * moves the same bytes.  In place, nsteps must be even (ESELBM_E_ARG), so
+ * that the result is in the usual layout, and the grid periodic, with the
+ * modes HIGHER, LOWER, BGK or LBGK and Pr = 1 (ESELBM_E_UNSUPPORTED
+ * otherwise).
  * With statistics enabled, the last step fills the accumulators. */
 eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, double tau,
                           void *stream);

@@ -204,11 +204,21 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
     }
     const size_t bytes = (size_t)h->g.Q * (size_t)h->g.N * elem_size(h->dtype);
     const char *a = (const char *)f_in, *b = (const char *)f_out;
-    if (a < b + bytes && b < a + bytes) return fail(ESELBM_E_ARG, "eselbm_step: f_in and f_out overlap");
+    const bool in_place = f_in == f_out;
+    if (!in_place && a < b + bytes && b < a + bytes) return fail(ESELBM_E_ARG, "eselbm_step: f_in and f_out overlap");
+    if (in_place) {
+        if (nsteps % 2) return fail(ESELBM_E_ARG, "eselbm_step: in-place stepping needs an even nsteps");
+        if (h->walls || cpr != 0.0) return fail(ESELBM_E_UNSUPPORTED, "eselbm_step: in-place stepping is periodic, without ES-BGK");
+        if (h->mode != ESELBM_MODE_HIGHER && h->mode != ESELBM_MODE_LOWER && h->mode != ESELBM_MODE_BGK &&
+            h->mode != ESELBM_MODE_LBGK)
+            return fail(ESELBM_E_UNSUPPORTED, "eselbm_step: in-place stepping takes the modes HIGHER, LOWER, BGK and LBGK");
+    }
     hipStream_t s = (hipStream_t)stream;
     // Step k reads one buffer and writes the other, starting f_in -> f_out;
     // after an even count the newest state is back in f_in and one copy
-    // moves it to f_out (f_in is documented as clobbered).
+    // moves it to f_out (f_in is documented as clobbered).  In place
+    // (f_in == f_out) the steps alternate the pull half and the local half
+    // of the AA pattern on the one buffer.
     void *src = f_in, *dst = f_out;
     for (int k = 0; k < nsteps; ++k) {
         const bool last = k == nsteps - 1;
@@ -224,6 +234,7 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
         sa.nut_out = last ? h->nut_field : nullptr;
         sa.stats = (last && h->stats_on) ? h->dev_stats : nullptr;
         sa.cpr = cpr;
+        sa.aa = in_place ? (k % 2 == 0 ? 1 : 2) : 0;
         const bool diag = sa.alpha_out != nullptr || sa.nut_out != nullptr || sa.stats != nullptr;
         if (sa.stats) {
             hipError_t e = launch_reset_stats(h->dev_stats, s);
@@ -231,9 +242,11 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
         }
         hipError_t e = launch_step(h->dtype, h->mode, diag, sa, s);
         if (e != hipSuccess) return hip_fail(e, "eselbm_step: launch");
-        void *t = src;
-        src = dst;
-        dst = t;
+        if (!in_place) {
+            void *t = src;
+            src = dst;
+            dst = t;
+        }
     }
     if (src != f_out) {
         hipError_t e = hipMemcpyAsync(f_out, src, bytes, hipMemcpyDeviceToDevice, s);

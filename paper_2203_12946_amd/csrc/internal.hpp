@@ -37,6 +37,7 @@ struct StepArgs {
     void *nut_out;       // [N] compute type or null: nu_T of Eq. nuT
     DevStats *stats;     // kStatSlots slots or null
     double cpr;          // ES-BGK stress factor c_Pr; 0: the equilibrium itself
+    int aa;              // 0: two lattices (fin -> fout); in place: 1 the pull half, 2 the local half
 };
 
 // Launchers (return the hipError_t of the launch).

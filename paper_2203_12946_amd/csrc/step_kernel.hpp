@@ -289,7 +289,18 @@ __device__ inline void pull_walls(const StepArgs &a, int x, int y, int z, typena
     }
 }
 
-template <int D, typename S, int MODE, bool DIAG, bool FORCE, bool WALL = false, bool QE = false>
+// In-place (AA) stepping on one lattice: pairs of launches, the first of
+// which reads every population from its source cell x - c_i (as the
+// two-lattice pull) and writes the post-collision population i back to the
+// slot it read for the opposite direction, slot opp(i) of cell x + c_i; the
+// second reads the populations of its own cell from the opposite slots and
+// writes them to their own slots.  Each launch touches every location from
+// one lane only (the one it reads is the one it writes), so it runs in place,
+// and after the pair the lattice holds the post-collision state in the
+// two-lattice layout.  kAAPull / kAALocal select the two launches.
+enum AAKind { kTwoLattice = 0, kAAPull = 1, kAALocal = 2 };
+
+template <int D, typename S, int MODE, bool DIAG, bool FORCE, bool WALL = false, bool QE = false, int AA = kTwoLattice>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_k<D, S, MODE, WALL, QE>()))) void k_step(StepArgs a)
 {
     using T = typename Storage<S>::T;
@@ -299,8 +310,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
     const long long N = a.g.N;
     const int y = (int)blockIdx.y, z = (int)blockIdx.z;
     const int x = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
-    const S *__restrict__ fin = (const S *)a.fin;
-    S *__restrict__ fout = (S *)a.fout;
+    // in place the two pointers are the same buffer: no restrict there
+    using InP = typename std::conditional<AA == kTwoLattice, const S *__restrict__, const S *>::type;
+    using OutP = typename std::conditional<AA == kTwoLattice, S *__restrict__, S *>::type;
+    InP fin = (const S *)a.fin;
+    OutP fout = (S *)a.fout;
     const T beta = (T)a.beta;
 
     LaneStats ls;
@@ -324,6 +338,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
         T p[Q];
         if constexpr (WALL) {
             pull_walls<D, S>(a, x, y, z, p);
+        } else if constexpr (AA == kAALocal) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) p[i] = Storage<S>::to_T(fin[(long long)(Q - 1 - i) * N + cell]);
         } else {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
@@ -406,9 +423,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
         // post-collision value p + alpha beta (feq - g) [+ force term]
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            S *orow = fout + ((long long)i * N + row0);
             const T v = Pol::ab_split || FORCE ? fma_(ab, dd[i], fma_(ab_lo, dd[i], p[i])) : fma_(ab, dd[i], p[i]);
-            Storage<S>::store_nt(lane_ptr(orow, (unsigned)x), v);
+            if constexpr (AA == kAAPull) {
+                // slot opp(i) of cell x + c_i, the location this lane read
+                // population opp(i) from
+                const int cx = 1 - Lat<D>::c(i, 0), cy = 1 - Lat<D>::c(i, 1), cz = 1 - Lat<D>::c(i, 2);
+                S *orow = fout + ((long long)(Q - 1 - i) * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
+                Storage<S>::store_nt(lane_ptr(orow, xs[cx]), v);
+            } else {
+                S *orow = fout + ((long long)i * N + row0);
+                Storage<S>::store_nt(lane_ptr(orow, (unsigned)x), v);
+            }
         }
 
         if (DIAG) {
@@ -454,6 +479,31 @@ static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
     if (a.g.ny > 65535 || a.g.nz > 65535) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)((a.g.nx + bx - 1) / bx), (unsigned)a.g.ny, (unsigned)a.g.nz), block(bx);
     const bool force = a.force != nullptr;
+    if (a.aa != kTwoLattice) {
+        // in place: periodic, the closed-form and alpha = 2 modes
+        if constexpr (MODE == MODE_HIGHER || MODE == MODE_LOWER || MODE == MODE_BGK || MODE == MODE_LBGK) {
+            if (a.walls || a.cpr != 0.0) return hipErrorInvalidValue;
+            if (force && !std::is_same<S, float>::value) return hipErrorInvalidValue;
+#define ESELBM_AA_LAUNCH(KIND)                                                                          \
+    do {                                                                                                \
+        if (force) {                                                                                    \
+            if constexpr (std::is_same<S, float>::value) {                                              \
+                if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, true, false, false, KIND>), grid, block, 0, s, a);  \
+                else hipLaunchKernelGGL((k_step<D, S, MODE, false, true, false, false, KIND>), grid, block, 0, s, a);      \
+            }                                                                                           \
+        } else if (diag) {                                                                              \
+            hipLaunchKernelGGL((k_step<D, S, MODE, true, false, false, false, KIND>), grid, block, 0, s, a);              \
+        } else {                                                                                        \
+            hipLaunchKernelGGL((k_step<D, S, MODE, false, false, false, false, KIND>), grid, block, 0, s, a);             \
+        }                                                                                               \
+    } while (0)
+            if (a.aa == kAAPull) ESELBM_AA_LAUNCH(kAAPull);
+            else ESELBM_AA_LAUNCH(kAALocal);
+#undef ESELBM_AA_LAUNCH
+            return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+    }
     if (a.cpr != 0.0) {
         // ES-BGK: periodic, unforced, path lengths alpha_Higher, alpha_Lower, 2
         if constexpr (MODE == MODE_HIGHER || MODE == MODE_LOWER || MODE == MODE_BGK) {
