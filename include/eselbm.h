@@ -37,9 +37,10 @@
  * nu = tau / 3 (Sec. II).  It must be > 0.
  *
  * Ownership: every buffer passed in is device memory owned by the caller.
- * The library never frees caller memory.  It owns only the handle and a
+ * The library never frees caller memory.  It owns only the handle, a
  * small (under 10 KiB) device block of diagnostic accumulators and the wall
- * table, which eselbm_create allocates and eselbm_destroy frees.
+ * table, which eselbm_create allocates, and the losses' scratch (allocated
+ * by the first loss call), all of which eselbm_destroy frees.
  *
  * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
  * stream.  All kernels are enqueued on it asynchronously.  Only
@@ -279,11 +280,11 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
  * the direct part of dL/dF (through the half-force shift of u) is ADDED to
  * force_grad (device float [D][cells]).  Any output may be NULL.  The loss
  * is summed in a fixed order (the same bits on every run).
- * Scratch: the first loss call on a grid allocates library-owned device
+ * Scratch: the first loss call on a handle allocates handle-owned device
  * fields of 7 floats per cell (u, rho, vorticity) and one double per 64-256
- * cells (partial sums), kept for later calls on grids no larger and released
- * when the process ends; calls on one device share them, so calls that
- * overlap on different streams race. */
+ * cells (partial sums) on the current device, kept until eselbm_destroy;
+ * loss calls on one handle share them, so such calls that overlap on
+ * different streams race (use one handle per concurrent stream). */
 eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
                                       double weight, void *force_grad, void *stream);
 

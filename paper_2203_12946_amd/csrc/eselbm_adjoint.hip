@@ -699,18 +699,6 @@ __global__ __launch_bounds__(256) void k_kinetic(Grid g, const S *__restrict__ f
     if (part) block_partial(e, part, blockIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Scratch of the losses, grown on demand (single device per process):
-// velocity and density of the state, vorticity, and one partial sum per block.
-// ---------------------------------------------------------------------------
-struct Scratch {
-    float *u = nullptr;      // [D][N], u = (j + F/2) / rho
-    float *rho = nullptr;    // [N]
-    float *vort = nullptr;   // [nv][N], nv = 1 (2-D) or 3 (3-D)
-    double *part = nullptr;  // one partial sum per block
-    long long cells = 0, parts = 0;
-};
-static Scratch g_scratch;
 
 // Blocks of the (x-block, y, z) launch used by the stencil passes; it is at
 // least the ceil(N / 256) blocks of the cell-local passes.
@@ -720,35 +708,49 @@ static long long stencil_blocks(const Grid &g)
     return (long long)((g.nx + bx - 1) / bx) * g.ny * g.nz;
 }
 
-static hipError_t ensure_scratch(const Grid &g)
+hipError_t free_loss_scratch(LossScratch &sc)
+{
+    hipError_t e = hipSuccess, r;
+    void *bufs[4] = {sc.u, sc.rho, sc.vort, sc.part};
+    for (void *b : bufs) {
+        if (!b) continue;
+        r = hipFree(b);
+        if (e == hipSuccess) e = r;
+    }
+    sc = LossScratch{};
+    return e;
+}
+
+// Grows the handle's scratch to the grid (hipFree waits for the work that
+// may still use the old buffers).
+static hipError_t ensure_scratch(LossScratch &sc, const Grid &g)
 {
     const long long parts = stencil_blocks(g);
-    if (g_scratch.cells >= g.N && g_scratch.parts >= parts) return hipSuccess;
-    hipFree(g_scratch.u);
-    hipFree(g_scratch.rho);
-    hipFree(g_scratch.vort);
-    hipFree(g_scratch.part);
-    g_scratch = Scratch{};
-    hipError_t e = hipMalloc((void **)&g_scratch.u, sizeof(float) * 3 * g.N);
-    if (e == hipSuccess) e = hipMalloc((void **)&g_scratch.rho, sizeof(float) * g.N);
-    if (e == hipSuccess) e = hipMalloc((void **)&g_scratch.vort, sizeof(float) * 3 * g.N);
-    if (e == hipSuccess) e = hipMalloc((void **)&g_scratch.part, sizeof(double) * parts);
-    if (e != hipSuccess) return e;
-    g_scratch.cells = g.N;
-    g_scratch.parts = parts;
+    if (sc.cells >= g.N && sc.parts >= parts) return hipSuccess;
+    hipError_t e = free_loss_scratch(sc);
+    if (e == hipSuccess) e = hipMalloc((void **)&sc.u, sizeof(float) * 3 * g.N);
+    if (e == hipSuccess) e = hipMalloc((void **)&sc.rho, sizeof(float) * g.N);
+    if (e == hipSuccess) e = hipMalloc((void **)&sc.vort, sizeof(float) * 3 * g.N);
+    if (e == hipSuccess) e = hipMalloc((void **)&sc.part, sizeof(double) * parts);
+    if (e != hipSuccess) {
+        free_loss_scratch(sc);
+        return e;
+    }
+    sc.cells = g.N;
+    sc.parts = parts;
     return hipSuccess;
 }
 
 template <int D>
-static hipError_t launch_kin_d(int dtype, const Grid &g, const void *f, double *loss, void *lam, double scale,
-                               hipStream_t s)
+static hipError_t launch_kin_d(LossScratch &sc, int dtype, const Grid &g, const void *f, double *loss, void *lam,
+                               double scale, hipStream_t s)
 {
-    hipError_t e = ensure_scratch(g);
+    hipError_t e = ensure_scratch(sc, g);
     if (e != hipSuccess) return e;
     const long long nblk = (g.N + 255) / 256;
     if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)nblk), block(256);
-    double *part = loss ? g_scratch.part : nullptr;
+    double *part = loss ? sc.part : nullptr;
     if (dtype == 0)
         hipLaunchKernelGGL((k_kinetic<D, double>), grid, block, 0, s, g, (const double *)f, part, (double *)lam, scale);
     else if (dtype == 1)
@@ -761,11 +763,11 @@ static hipError_t launch_kin_d(int dtype, const Grid &g, const void *f, double *
     return hipGetLastError();
 }
 
-hipError_t launch_kinetic_loss(int dtype, const Grid &g, const void *f, double *loss, void *lam, double scale,
-                               hipStream_t s)
+hipError_t launch_kinetic_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, double *loss, void *lam,
+                               double scale, hipStream_t s)
 {
-    return g.D == 2 ? launch_kin_d<2>(dtype, g, f, loss, lam, scale, s)
-                    : launch_kin_d<3>(dtype, g, f, loss, lam, scale, s);
+    return g.D == 2 ? launch_kin_d<2>(sc, dtype, g, f, loss, lam, scale, s)
+                    : launch_kin_d<3>(sc, dtype, g, f, loss, lam, scale, s);
 }
 
 // ---------------------------------------------------------------------------
@@ -920,47 +922,48 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restri
 }
 
 template <int D>
-static hipError_t launch_diss_d(int dtype, const Grid &g, const void *f, const float *force, double *loss, void *lam,
-                                void *seed, double weight, float *force_grad, hipStream_t s)
+static hipError_t launch_diss_d(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *force,
+                                double *loss, void *lam, void *seed, double weight, float *force_grad, hipStream_t s)
 {
-    hipError_t e = ensure_scratch(g);
+    hipError_t e = ensure_scratch(sc, g);
     if (e != hipSuccess) return e;
     const long long nflat = (g.N + 255) / 256;
     if (nflat > 0x7fffffffLL || g.ny > 65535 || g.nz > 65535) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)nflat), block(256);
     if (dtype == 0)
-        hipLaunchKernelGGL((k_velocity<D, double>), grid, block, 0, s, g, (const double *)f, force, g_scratch.u,
-                           g_scratch.rho);
+        hipLaunchKernelGGL((k_velocity<D, double>), grid, block, 0, s, g, (const double *)f, force, sc.u,
+                           sc.rho);
     else if (dtype == 1)
-        hipLaunchKernelGGL((k_velocity<D, float>), grid, block, 0, s, g, (const float *)f, force, g_scratch.u,
-                           g_scratch.rho);
+        hipLaunchKernelGGL((k_velocity<D, float>), grid, block, 0, s, g, (const float *)f, force, sc.u,
+                           sc.rho);
     else if (dtype == 3)
-        hipLaunchKernelGGL((k_velocity<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, g_scratch.u,
-                           g_scratch.rho);
+        hipLaunchKernelGGL((k_velocity<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, sc.u,
+                           sc.rho);
     else
         return hipErrorInvalidValue;
     const int bx = block_x(g.nx);
     const dim3 sgrid((unsigned)((g.nx + bx - 1) / bx), (unsigned)g.ny, (unsigned)g.nz), sblock(bx);
-    double *part = loss ? g_scratch.part : nullptr;
-    hipLaunchKernelGGL((k_vorticity<D>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.vort, part, weight);
+    double *part = loss ? sc.part : nullptr;
+    hipLaunchKernelGGL((k_vorticity<D>), sgrid, sblock, 0, s, g, sc.u, sc.vort, part, weight);
     if (loss)
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (const double *)part, stencil_blocks(g), loss);
     if (lam || seed || force_grad) {
         if (dtype == 0)
-            hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.rho,
-                               g_scratch.vort, (double *)lam, (double *)seed, weight, force_grad);
+            hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, sc.u, sc.rho,
+                               sc.vort, (double *)lam, (double *)seed, weight, force_grad);
         else
-            hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, g_scratch.u, g_scratch.rho,
-                               g_scratch.vort, (float *)lam, (float *)seed, weight, force_grad);
+            hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, sc.u, sc.rho,
+                               sc.vort, (float *)lam, (float *)seed, weight, force_grad);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_dissipation_loss(int dtype, const Grid &g, const void *f, const float *force, double *loss,
-                                   void *lam, void *seed, double weight, float *force_grad, hipStream_t s)
+hipError_t launch_dissipation_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *force,
+                                   double *loss, void *lam, void *seed, double weight, float *force_grad,
+                                   hipStream_t s)
 {
-    return g.D == 2 ? launch_diss_d<2>(dtype, g, f, force, loss, lam, seed, weight, force_grad, s)
-                    : launch_diss_d<3>(dtype, g, f, force, loss, lam, seed, weight, force_grad, s);
+    return g.D == 2 ? launch_diss_d<2>(sc, dtype, g, f, force, loss, lam, seed, weight, force_grad, s)
+                    : launch_diss_d<3>(sc, dtype, g, f, force, loss, lam, seed, weight, force_grad, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -28,6 +28,7 @@ struct eselbm_ctx {
     int walls;             // bit a: axis a bounded by diffuse walls
     double *wall_eq;       // device [2 D][Q], inside the dev_stats allocation
     double prandtl;        // ES-BGK Prandtl number; 1: the equilibrium itself
+    LossScratch loss_scratch;  // the losses' buffers on this handle's device, grown on demand
 };
 
 static thread_local std::string g_err;
@@ -64,7 +65,7 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
     if (N > (1LL << 40)) return fail(ESELBM_E_ARG, "eselbm_create: grid too large");
     eselbm_ctx *h = new (std::nothrow) eselbm_ctx;
     if (!h) return fail(ESELBM_E_ARG, "eselbm_create: out of host memory");
-    std::memset(h, 0, sizeof(*h));
+    std::memset((void *)h, 0, sizeof(*h));
     h->g = Grid{lattice == ESELBM_D2Q9 ? 2 : 3, Q, nx, ny, nz, N};
     h->dtype = dtype;
     h->mode = ESELBM_MODE_HIGHER;
@@ -88,6 +89,8 @@ eselbm_status eselbm_destroy(eselbm_handle h)
 {
     if (!h) return ESELBM_OK;
     hipError_t e = hipFree(h->dev_stats);
+    hipError_t e2 = free_loss_scratch(h->loss_scratch);
+    if (e == hipSuccess) e = e2;
     delete h;
     if (e != hipSuccess) return hip_fail(e, "eselbm_destroy: hipFree");
     return ESELBM_OK;
@@ -344,7 +347,7 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
 {
     if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_kinetic_loss: NULL argument");
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_kinetic_loss: F16 storage");
-    hipError_t e = launch_kinetic_loss(h->dtype, h->g, f, loss_dev, lam, scale, (hipStream_t)stream);
+    hipError_t e = launch_kinetic_loss(h->loss_scratch, h->dtype, h->g, f, loss_dev, lam, scale, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_kinetic_loss: launch");
     return ESELBM_OK;
 }
@@ -356,7 +359,7 @@ eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *lo
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: force_grad without a registered force");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: periodic differences only");
-    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, loss_dev, lam, nullptr, weight,
+    hipError_t e = launch_dissipation_loss(h->loss_scratch, h->dtype, h->g, f, h->force, loss_dev, lam, nullptr, weight,
                                            (float *)force_grad, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_loss: launch");
     return ESELBM_OK;
@@ -369,7 +372,7 @@ eselbm_status eselbm_dissipation_seed(eselbm_handle h, const void *f, void *seed
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: force_grad without a registered force");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: periodic differences only");
-    hipError_t e = launch_dissipation_loss(h->dtype, h->g, f, h->force, nullptr, nullptr, seed, weight,
+    hipError_t e = launch_dissipation_loss(h->loss_scratch, h->dtype, h->g, f, h->force, nullptr, nullptr, seed, weight,
                                            (float *)force_grad, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_seed: launch");
     return ESELBM_OK;

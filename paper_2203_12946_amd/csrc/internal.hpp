@@ -65,9 +65,20 @@ struct AdjArgs {
     const void *seed;  // compute type [1 + D][N] or null: lam_next_i += s0 + c_i . s
 };
 hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s);
-hipError_t launch_kinetic_loss(int dtype, const Grid &g, const void *f, double *loss, void *lam,
+// Scratch of the losses, owned by a handle (so by its device) and grown on
+// demand: velocity and density of the state, vorticity, and one partial sum
+// per block.
+struct LossScratch {
+    float *u = nullptr;      // [D][N], u = (j + F/2) / rho
+    float *rho = nullptr;    // [N]
+    float *vort = nullptr;   // [nv][N], nv = 1 (2-D) or 3 (3-D)
+    double *part = nullptr;  // one partial sum per block
+    long long cells = 0, parts = 0;
+};
+hipError_t free_loss_scratch(LossScratch &sc);
+hipError_t launch_kinetic_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, double *loss, void *lam,
                                double scale, hipStream_t s);
-hipError_t launch_dissipation_loss(int dtype, const Grid &g, const void *f, const float *force,
+hipError_t launch_dissipation_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *force,
                                    double *loss, void *lam, void *seed, double weight, float *force_grad,
                                    hipStream_t s);
 hipError_t launch_equilibrium_vjp(int dtype, const Grid &g, const double *rho, const double *u,
