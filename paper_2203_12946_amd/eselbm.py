@@ -217,6 +217,11 @@ class Solver:
                                int(nsteps), float(tau), _stream(stream)))
 
     def stats(self, with_H: bool = False, stream=None) -> dict:
+        """FP64 diagnostics of the last statistics-enabled step (synchronises
+        the stream).  A step that met non-positive or non-finite populations
+        is not an error here: the counts are returned with ``status`` set to
+        E_NONPOSITIVE and ``n_nonpos`` > 0, so that a caller can stop a run
+        that has lost positivity; every other failure raises EselbmError."""
         st = Stats()
         status = lib.eselbm_alpha_stats(self._h, ctypes.byref(st), int(bool(with_H)), _stream(stream))
         if status not in (OK, E_NONPOSITIVE):
