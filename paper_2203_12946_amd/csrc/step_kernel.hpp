@@ -209,10 +209,15 @@ constexpr int step_waves_qe()
 // node's mass balance live beside the two Q-arrays: two waves per SIMD for
 // D2Q9 in single precision, one for D3Q27 or in double, which removes the
 // spills the periodic step's occupancy floor would force on it.
-template <int D, typename S, int MODE, bool WALL, bool QE>
+//
+// The forced step evaluates two more equilibria (at u and u + F/rho) while d
+// and the stored values are live: at the periodic step's four waves its
+// common path would spill, so it runs at three.
+template <int D, typename S, int MODE, bool WALL, bool QE, bool FORCE>
 constexpr int step_waves_k()
 {
-    return WALL ? ((D == 3 || StepPolicy<S>::eq_f64) ? 1 : 2) : step_waves_qe<D, S, MODE, QE>();
+    return WALL ? ((D == 3 || StepPolicy<S>::eq_f64) ? 1 : 2)
+                : (FORCE && step_waves_qe<D, S, MODE, QE>() > 3 ? 3 : step_waves_qe<D, S, MODE, QE>());
 }
 
 // Pull with diffuse walls (the boundary rule of the lid-driven cavity,
@@ -301,7 +306,7 @@ __device__ inline void pull_walls(const StepArgs &a, int x, int y, int z, typena
 enum AAKind { kTwoLattice = 0, kAAPull = 1, kAALocal = 2 };
 
 template <int D, typename S, int MODE, bool DIAG, bool FORCE, bool WALL = false, bool QE = false, int AA = kTwoLattice>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_k<D, S, MODE, WALL, QE>()))) void k_step(StepArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_k<D, S, MODE, WALL, QE, FORCE>()))) void k_step(StepArgs a)
 {
     using T = typename Storage<S>::T;
     using Pol = StepPolicy<S>;
