@@ -318,24 +318,6 @@ __device__ inline void equilibrium_shifted(T drho, const T (&u)[3], T (&feqt)[La
     }
 }
 
-// Moments of a shifted state: drho = sum g~ (sum w = 1), j = sum g~ c
-// (sum w c = 0).
-template <int D, typename T>
-__device__ inline void moments_shifted(const T (&gt)[Lat<D>::Q], T &drho, T (&j)[3])
-{
-    drho = T(0);
-    j[0] = j[1] = j[2] = T(0);
-#pragma unroll
-    for (int i = 0; i < Lat<D>::Q; ++i) {
-        drho += gt[i];
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-            if (Lat<D>::c(i, a) > 0) j[a] += gt[i];
-            if (Lat<D>::c(i, a) < 0) j[a] -= gt[i];
-        }
-    }
-}
-
 struct CellInfo {
     int gated, guarded, exact;  // exact: the exact rational path ran
     int iters, fallback;        // mirror modes: Newton iterations; alpha_Lower kept
