@@ -213,7 +213,16 @@ def cpu_baseline(W, wl, seconds_target: float = 15.0):
         value1, nsteps1, dt1 = timed(2, 0.5 * seconds_target)
     finally:
         oracle.set_threads(0)
-    return dict(value=value, unit="MLUPS", cores=threads, kind="oracle",
+    cpu_model = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu_model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return dict(value=value, unit="MLUPS", cores=threads, kind="oracle", cpu_model=cpu_model,
+                nproc=os.cpu_count(), omp_num_threads=os.environ.get("OMP_NUM_THREADS"),
                 sample=f"{wl.shape[2]}x{wl.shape[1]}x16 z-slab of the {wl.name} workload, {nsteps} steps, FP64, "
                        f"{dt:.1f} s on {threads} threads; one core: {wl.shape[2]}x{wl.shape[1]}x2 slab, "
                        f"{nsteps1} steps, {dt1:.1f} s",
