@@ -34,6 +34,9 @@ METRIC = "ESELBM MLUPS & % HBM roofline (D3Q27 FP32 vs FP64); adjoint/forward ti
 KERNEL_SOURCES = ["paper_2203_12946_amd/csrc/step_kernel.hpp", "paper_2203_12946_amd/csrc/step_f32.hip",
                   "paper_2203_12946_amd/csrc/lattice.hpp", "paper_2203_12946_amd/csrc/quasi_eq.hpp"]
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_d3q27_f32_256.md"
+VALU_FILE = ROOT / "profiles" / "valu_issue_d3q27_f32.md"
+# VALU issue peak: 1024 SIMD16s at 2.4 GHz, 4 cycles per wave64 instruction
+VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
 
 def _log(msg: str):
@@ -45,6 +48,35 @@ def kernel_hash() -> str:
     for p in KERNEL_SOURCES:
         h.update((ROOT / p).read_bytes())
     return h.hexdigest()[:16]
+
+
+def _profile_values(path):
+    """The machine-readable block of a committed profile summary, or None
+    once the kernel sources have changed since it was taken."""
+    if not path.exists():
+        return None
+    kv = {}
+    for line in path.read_text().splitlines():
+        k, sep, v = line.strip().partition(": ")
+        if sep:
+            kv[k] = v.strip()
+    if kv.get("kernel_hash") != kernel_hash():
+        return None
+    return kv
+
+
+def alu_roofline(kernel_ms: float):
+    """Second roofline of the headline step: its measured VALU instructions per
+    launch (committed counter summary) at the chip's issue rate, against the
+    kernel time; None once the kernel sources have changed."""
+    kv = _profile_values(VALU_FILE)
+    if kv is None:
+        return None
+    instr = float(kv["valu_per_wave"]) * float(kv["waves_per_launch"])
+    floor_ms = instr / VALU_WAVE_INSTR_PER_S * 1e3
+    return {"bound": "alu", "issue_floor_ms": round(floor_ms, 4), "kernel_ms": round(kernel_ms, 4),
+            "frac": round(floor_ms / kernel_ms, 4), "valu_per_wave": float(kv["valu_per_wave"]),
+            "peak": "614.4 G wave64 VALU instructions/s"}
 
 
 def traffic_bytes():
@@ -362,6 +394,7 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                      "kernel_ms": round(main_run["kernel_ms"], 4), "bytes_per_cell": bytes_per_cell,
                      "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)},
+        "alu_roofline": alu_roofline(main_run["kernel_ms"]),
         "cpu_baseline": cpu,
         "variants": variants,
         "adjoint": adj,
