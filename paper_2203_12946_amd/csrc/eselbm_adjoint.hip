@@ -18,6 +18,8 @@
 #include "internal.hpp"
 #include "lattice.hpp"
 
+#include <type_traits>
+
 namespace eselbm {
 
 template <typename V>
@@ -501,9 +503,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
         // Per population, (dir, xd): the explicit g-derivative of the
         // path-length sums at fixed x, and their x-derivative over g (the
         // guard's x_min population alone where the guard fired).  Two passes
-        // over the populations with the same (dir, xd): the first gathers the
-        // adjoints of rho and u through feq = rho P(u), the second forms mu_i
-        // and pushes it out, so that no Q-array of mu is live.
+        // over the populations: the first gathers the adjoints of rho and u
+        // through feq = rho P(u), the second forms mu_i and pushes it out, so
+        // that no Q-array of mu is live.  In single precision the first pass
+        // also keeps the lambda-free part of mu_i, dir_i - (1 + x_i) xd_i, in
+        // the register of x_i, so that (dir, xd) are formed once; in double
+        // precision the second pass forms them again (the double kernels keep
+        // the form they were validated in).
         T F[3][3], dF[3][3];
         axis_factors_d<D, T>(u, F, dF);
         const T xdmin = guarded ? xminb * rcp_(gxm) : T(0);
@@ -515,16 +521,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
             return xi;
         };
         auto passes = [&](auto &&dirxd) {
+            constexpr bool keep_mu = !std::is_same<T, double>::value;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 T dir, xd;
-                dirxd(xcopy(i), dir, xd);
+                const T xi = xcopy(i);
+                dirxd(xi, dir, xd);
                 if (guarded && i == imin) xd = xdmin;
                 T gp[3];
                 const T Pi = prod_and_grad<D, T>(i, F, dF, gp);
                 rhob = fma_(xd, Pi, rhob);
 #pragma unroll
                 for (int c = 0; c < D; ++c) ub[c] = fma_(xd, gp[c], ub[c]);
+                if constexpr (keep_mu) v[i] = fma_(-(T(1) + xi), xd, dir);
                 __builtin_amdgcn_sched_barrier(0);
             }
             // feq = rho P(u): dfeq/du = rho dP/du; the force term's u_f; then
@@ -543,11 +552,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
             for (int i = 0; i < Q; ++i) l[i] = lam_at(i);
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                T dir, xd;
-                const T xi = xcopy(i);
-                dirxd(xi, dir, xd);
-                if (guarded && i == imin) xd = xdmin;
-                T m = fma_(l[i], T(1) - ab, dir) - (T(1) + xi) * xd + rhob;
+                T m;
+                if constexpr (keep_mu) {
+                    m = fma_(l[i], T(1) - ab, v[i]) + rhob;
+                } else {
+                    T dir, xd;
+                    const T xi = xcopy(i);
+                    dirxd(xi, dir, xd);
+                    if (guarded && i == imin) xd = xdmin;
+                    m = fma_(l[i], T(1) - ab, dir) - (T(1) + xi) * xd + rhob;
+                }
 #pragma unroll
                 for (int c = 0; c < D; ++c) {
                     if (Lat<D>::c(i, c) > 0) m += jb[c];
