@@ -63,7 +63,8 @@ def test_in_place_equals_two_lattices(es, D, shape, mode, dtype):
     assert same
     for k in ("n_gated", "n_guard", "n_exact", "n_nonpos"):
         assert st1[k] == st2[k]
-    assert st1["mass"] == st2["mass"]
+    # the FP64 mass is summed with atomics, in an order that varies
+    assert abs(st1["mass"] - st2["mass"]) <= 1e-13 * abs(st2["mass"])
 
 
 def test_in_place_with_force(es):
