@@ -139,9 +139,11 @@ typedef struct {
 
 /* Creates a solver for an nx * ny * nz periodic grid (nz must be 1 for
  * D2Q9).  Allocates the accumulator block on the current device.
- * Errors: ESELBM_E_ARG for a NULL out, dims < 1, unknown lattice or dtype,
- * or a grid whose state does not fit a 63-bit index; ESELBM_E_UNSUPPORTED
- * for ny or nz above 65535 (the step launches one block row per (y, z)). */
+ * Errors: ESELBM_E_ARG for a NULL out, dims < 1, unknown lattice or dtype;
+ * ESELBM_E_UNSUPPORTED for ny or nz above 65535 (the step launches one block
+ * row per (y, z)) or more than 2^32 - 2^16 cells (the cell-wise passes use a
+ * 1-D launch, whose size in work-items is 32-bit; at 4 B per population a
+ * D3Q27 lattice of that many cells would already take 464 GB). */
 eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int nz, int dtype);
 
 /* Frees the handle and its accumulator block.  NULL is accepted. */

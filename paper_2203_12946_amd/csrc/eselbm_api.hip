@@ -62,7 +62,9 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
     if (ny > 65535 || nz > 65535) return fail(ESELBM_E_UNSUPPORTED, "eselbm_create: ny and nz must be <= 65535");
     const int Q = lattice == ESELBM_D2Q9 ? 9 : 27;
     const long long N = (long long)nx * ny * nz;
-    if (N > (1LL << 40)) return fail(ESELBM_E_ARG, "eselbm_create: grid too large");
+    // the cell-wise passes launch one work-item per cell in a 1-D grid, whose
+    // size in work-items is a 32-bit quantity
+    if (N > 0xFFFF0000LL) return fail(ESELBM_E_UNSUPPORTED, "eselbm_create: grids of more than 2^32 - 2^16 cells");
     eselbm_ctx *h = new (std::nothrow) eselbm_ctx;
     if (!h) return fail(ESELBM_E_ARG, "eselbm_create: out of host memory");
     std::memset((void *)h, 0, sizeof(*h));
