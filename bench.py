@@ -135,6 +135,44 @@ def time_forward(es, torch, W, wl, dtype: str, mode: str, steps: int, warmup: in
                 kernel_ms=kernel_ms, stats=st)
 
 
+def time_big_in_place(es, torch, W, n: int, steps: int):
+    """In-place steps of an n^3 D3Q27 FP32 lattice (one lattice of
+    27 * 4 * n^3 bytes), fields built on the device."""
+    u0 = 0.1 / math.sqrt(3.0)
+    s = es.Solver("D3Q27", (n, n, n), dtype="f32", mode="higher")
+    f = s.empty_state()
+    c = torch.arange(n, dtype=torch.float64, device="cuda") * (2 * math.pi / n)
+    cz, cy, cx = c.view(n, 1, 1), c.view(1, n, 1), c.view(1, 1, n)
+    rho = 1 + 3 * (u0 ** 2 / 16) * (torch.cos(2 * cx) + torch.cos(2 * cy)) * (torch.cos(2 * cz) + 2)
+    u = torch.empty((3, n, n, n), dtype=torch.float64, device="cuda")
+    u[0] = u0 * torch.sin(cx) * torch.cos(cy) * torch.cos(cz)
+    u[1] = -u0 * torch.cos(cx) * torch.sin(cy) * torch.cos(cz)
+    u[2] = 0
+    s.init_equilibrium(rho.contiguous(), u, out=f)
+    del rho, u
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    tau = W.tau_from_nu(u0 * (n / (2 * math.pi)) / 1600.0)
+    steps += steps % 2
+    s.step(f, f, 4, tau)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps // 2):
+        s.step(f, f, 2, tau)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    cells = n ** 3
+    gbs = 216 * cells / (ms * 1e-3) / 1e9
+    del f, s
+    torch.cuda.empty_cache()
+    return dict(mlups=round(cells / ms / 1e3, 1), kernel_ms=round(ms, 4), hbm_gbs=round(gbs, 1),
+                frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_cell=216, state_gb=round(108 * cells / 1e9, 1))
+
+
 def copy_bandwidth(torch, nbytes: int, reps: int = 20):
     """Plain device-to-device copy of the same footprint as one step's state
     (read nbytes + write nbytes): the practical streaming ceiling, and the
@@ -328,6 +366,12 @@ def main():
                 hbm_gbs=round(gbs, 1), frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_cell=bpc,
                 n_gated=r["stats"]["n_gated"], n_exact=r["stats"]["n_exact"])
             _log(f"bench: {dtype} in place {r['mlups']:.0f} MLUPS")
+        # the largest lattice one GPU holds for this workload: 1024^3 in place
+        # (116 GB of FP32 populations), Taylor-Green without noise
+        _log("bench: 1024^3 f32 higher in place")
+        r = time_big_in_place(es, torch, W, 1024, max(10, args.steps // 10))
+        variants["d3q27_tgv_1024_f32_higher_in_place"] = r
+        _log(f"bench: 1024^3 in place {r['mlups']:.0f} MLUPS")
         # entropic ES-BGK (quasi-equilibrium solved per cell) at Pr = 0.71
         for dtype, bpc in (("f32", 216), ("f64", 432)):
             _log(f"bench: {dtype} higher ES-BGK")
