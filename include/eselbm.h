@@ -46,6 +46,14 @@
  * stream.  All kernels are enqueued on it asynchronously.  Only
  * eselbm_alpha_stats synchronises (that stream only).
  *
+ * Devices: a handle belongs to the device that is current when
+ * eselbm_create runs; its device memory lives there, and so must the
+ * caller's buffers and stream.  Every entry point that enqueues work or
+ * copies to the device (set_walls, init_equilibrium, step, alpha_stats,
+ * moments, adjoint_step, the losses, equilibrium_vjp) returns ESELBM_E_ARG,
+ * enqueueing nothing, when another device is current.  eselbm_destroy makes
+ * the handle's device current for its frees and restores the caller's.
+ *
  * Errors: every entry point returns an eselbm_status.  Nothing aborts or
  * throws across the ABI.  Argument errors are detected before anything is
  * enqueued.  Kernel faults surface as ESELBM_E_HIP at the next synchronising

@@ -45,6 +45,21 @@ static eselbm_status hip_fail(hipError_t e, const char *where)
     return ESELBM_E_HIP;
 }
 
+// The handle's device memory, and the caller's buffers and stream that go
+// with it, belong to the device that was current at eselbm_create; a call
+// made with another device current would launch there on foreign pointers.
+static eselbm_status device_check(const eselbm_ctx *h, const char *where)
+{
+    int cur = -1;
+    const hipError_t e = hipGetDevice(&cur);
+    if (e != hipSuccess) return hip_fail(e, where);
+    if (cur != h->device) {
+        g_err = std::string(where) + ": the current device is not the one the handle was created on";
+        return ESELBM_E_ARG;
+    }
+    return ESELBM_OK;
+}
+
 static size_t elem_size(int dtype) { return dtype == ESELBM_F64 ? 8 : (dtype == ESELBM_F16_SHIFTED ? 2 : 4); }
 
 extern "C" {
@@ -90,9 +105,16 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
 eselbm_status eselbm_destroy(eselbm_handle h)
 {
     if (!h) return ESELBM_OK;
-    hipError_t e = hipFree(h->dev_stats);
+    int cur = -1;
+    hipError_t e = hipGetDevice(&cur);
+    if (e == hipSuccess && cur != h->device) e = hipSetDevice(h->device);
+    if (e == hipSuccess) e = hipFree(h->dev_stats);
     hipError_t e2 = free_loss_scratch(h->loss_scratch);
     if (e == hipSuccess) e = e2;
+    if (cur >= 0 && cur != h->device) {
+        e2 = hipSetDevice(cur);
+        if (e == hipSuccess) e = e2;
+    }
     delete h;
     if (e != hipSuccess) return hip_fail(e, "eselbm_destroy: hipFree");
     return ESELBM_OK;
@@ -138,6 +160,7 @@ eselbm_status eselbm_set_prandtl(eselbm_handle h, double prandtl)
 eselbm_status eselbm_set_walls(eselbm_handle h, int walls, const double *velocity)
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_set_walls: NULL handle");
+    if (eselbm_status st = device_check(h, "eselbm_set_walls")) return st;
     const int D = h->g.D, Q = h->g.Q;
     if (walls < 0 || walls >= (1 << D)) return fail(ESELBM_E_ARG, "eselbm_set_walls: mask has bits beyond the lattice's axes");
     if (walls && h->force) return fail(ESELBM_E_UNSUPPORTED, "eselbm_set_walls: walls with a body force");
@@ -188,6 +211,7 @@ eselbm_status eselbm_init_equilibrium(eselbm_handle h, const double *rho, const 
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_init_equilibrium: NULL handle");
     if (!rho || !u || !f) return fail(ESELBM_E_ARG, "eselbm_init_equilibrium: NULL buffer");
+    if (eselbm_status st = device_check(h, "eselbm_init_equilibrium")) return st;
     hipError_t e = launch_init_eq(h->dtype, h->g, rho, u, f, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_init_equilibrium: launch");
     return ESELBM_OK;
@@ -197,6 +221,7 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_step: NULL handle");
     if (!f_in || !f_out) return fail(ESELBM_E_ARG, "eselbm_step: NULL state buffer");
+    if (eselbm_status st = device_check(h, "eselbm_step")) return st;
     if (nsteps < 1) return fail(ESELBM_E_ARG, "eselbm_step: nsteps must be >= 1");
     if (h->force && h->mode == ESELBM_MODE_LBGK) return fail(ESELBM_E_UNSUPPORTED, "eselbm_step: forcing in the classic LBGK mode");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_step: tau must be finite and > 0");
@@ -268,6 +293,7 @@ eselbm_status eselbm_alpha_stats(eselbm_handle h, eselbm_stats *out, int with_H,
 {
     if (!h || !out) return fail(ESELBM_E_ARG, "eselbm_alpha_stats: NULL argument");
     if (!h->have_stats) return fail(ESELBM_E_ARG, "eselbm_alpha_stats: no statistics-enabled step has run");
+    if (eselbm_status st = device_check(h, "eselbm_alpha_stats")) return st;
     hipStream_t s = (hipStream_t)stream;
     if (with_H) {
         hipError_t e = launch_H(h->dtype, h->g, h->last_out, h->dev_stats, s);
@@ -312,6 +338,7 @@ eselbm_status eselbm_alpha_stats(eselbm_handle h, eselbm_stats *out, int with_H,
 eselbm_status eselbm_moments(eselbm_handle h, const void *f, double *rho, double *u, void *stream)
 {
     if (!h || !f || !rho || !u) return fail(ESELBM_E_ARG, "eselbm_moments: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_moments")) return st;
     hipError_t e = launch_moments(h->dtype, h->g, f, h->force, rho, u, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_moments: launch");
     return ESELBM_OK;
@@ -321,6 +348,7 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
                                   void *lam_n, double tau, void *force_grad, void *stream)
 {
     if (!h || !f_n || !lam_next || !lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_adjoint_step")) return st;
     if (lam_next == lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: lam_n must not alias lam_next");
     if (seed_next && seed_next == lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: lam_n must not alias seed_next");
     if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: tau must be finite and > 0");
@@ -348,6 +376,7 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
                                   void *stream)
 {
     if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_kinetic_loss: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_kinetic_loss")) return st;
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_kinetic_loss: F16 storage");
     hipError_t e = launch_kinetic_loss(h->loss_scratch, h->dtype, h->g, f, loss_dev, lam, scale, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_kinetic_loss: launch");
@@ -358,6 +387,7 @@ eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *lo
                                       void *force_grad, void *stream)
 {
     if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_dissipation_loss")) return st;
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: force_grad without a registered force");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: periodic differences only");
@@ -371,6 +401,7 @@ eselbm_status eselbm_dissipation_seed(eselbm_handle h, const void *f, void *seed
                                       void *stream)
 {
     if (!h || !f || !seed) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_dissipation_seed")) return st;
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: force_grad without a registered force");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: periodic differences only");
@@ -384,6 +415,7 @@ eselbm_status eselbm_equilibrium_vjp(eselbm_handle h, const double *rho, const d
                                      double *grad_u, void *stream)
 {
     if (!h || !rho || !u || !lam || !grad_u) return fail(ESELBM_E_ARG, "eselbm_equilibrium_vjp: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_equilibrium_vjp")) return st;
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_equilibrium_vjp: F16 storage");
     hipError_t e = launch_equilibrium_vjp(h->dtype, h->g, rho, u, lam, grad_u, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_equilibrium_vjp: launch");

@@ -7,6 +7,7 @@ there is no fallback path.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import pathlib
 
@@ -98,12 +99,14 @@ def _check(status: int):
         raise EselbmError(status, lib.eselbm_last_error().decode())
 
 
-def _dev(t: torch.Tensor | None, dtype=None, numel=None) -> _vp:
+def _dev(t: torch.Tensor | None, dtype=None, numel=None, device=None) -> _vp:
     """Pointer of a contiguous device tensor (or NULL)."""
     if t is None:
         return _vp(None)
     if not t.is_cuda:
         raise ValueError("expected a device tensor")
+    if device is not None and t.device != device:
+        raise ValueError(f"expected a tensor on {device}, got one on {t.device}")
     if not t.is_contiguous():
         raise ValueError("expected a contiguous tensor")
     if dtype is not None and t.dtype != dtype:
@@ -159,23 +162,36 @@ class Solver:
             self._lib.eselbm_destroy(h)
             self._h = _vp()
 
+    def _p(self, t, dtype=None, numel=None) -> _vp:
+        return _dev(t, dtype, numel, self.device)
+
+    def _on(self):
+        """Makes the solver's device current for one library call (the
+        library rejects calls made with another device current)."""
+        if torch.cuda.current_device() == self.device.index:
+            return contextlib.nullcontext()
+        return torch.cuda.device(self.device)
+
     # ---- configuration --------------------------------------------------
     def set_mode(self, mode: str):
         self.mode = mode
         _check(lib.eselbm_set_mode(self._h, MODES[mode]))
 
     def set_stats(self, on: bool):
-        _check(lib.eselbm_set_stats(self._h, int(bool(on))))
+        with self._on():
+            _check(lib.eselbm_set_stats(self._h, int(bool(on))))
 
     def set_alpha_field(self, alpha: torch.Tensor | None):
         """Register a [*shape] compute-dtype tensor receiving per-cell alpha."""
         self._alpha = alpha
-        _check(lib.eselbm_set_alpha_field(self._h, _dev(alpha, self.compute_dtype, self.cells)))
+        with self._on():
+            _check(lib.eselbm_set_alpha_field(self._h, self._p(alpha, self.compute_dtype, self.cells)))
 
     def set_nut_field(self, nut: torch.Tensor | None):
         """Register a [*shape] compute-dtype tensor receiving per-cell nu_T (Eq. nuT)."""
         self._nut = nut
-        _check(lib.eselbm_set_nut_field(self._h, _dev(nut, self.compute_dtype, self.cells)))
+        with self._on():
+            _check(lib.eselbm_set_nut_field(self._h, self._p(nut, self.compute_dtype, self.cells)))
 
     def set_walls(self, walls=None, velocity=None):
         """Diffuse walls: ``walls`` per axis (x, y[, z]) True/False (None: none);
@@ -185,16 +201,19 @@ class Solver:
         for (a, sd), v in (velocity or {}).items():
             for k, comp in enumerate(v):
                 uw[(2 * a + sd) * 3 + k] = float(comp)
-        _check(lib.eselbm_set_walls(self._h, mask, ctypes.cast(uw, _vp)))
+        with self._on():
+            _check(lib.eselbm_set_walls(self._h, mask, ctypes.cast(uw, _vp)))
 
     def set_prandtl(self, prandtl: float):
         """Entropic ES-BGK collision at Prandtl number ``prandtl`` (1: off)."""
-        _check(lib.eselbm_set_prandtl(self._h, float(prandtl)))
+        with self._on():
+            _check(lib.eselbm_set_prandtl(self._h, float(prandtl)))
 
     def set_force(self, F: torch.Tensor | None):
         """Register a [D, *shape] float32 body-force density (F32 storage only)."""
         self._force = F
-        _check(lib.eselbm_set_force(self._h, _dev(F, torch.float32, self.D * self.cells)))
+        with self._on():
+            _check(lib.eselbm_set_force(self._h, self._p(F, torch.float32, self.D * self.cells)))
 
     # ---- state ----------------------------------------------------------
     def empty_state(self) -> torch.Tensor:
@@ -206,15 +225,17 @@ class Solver:
     def init_equilibrium(self, rho: torch.Tensor, u: torch.Tensor, out: torch.Tensor | None = None,
                          stream=None) -> torch.Tensor:
         f = self.empty_state() if out is None else out
-        _check(lib.eselbm_init_equilibrium(
-            self._h, _dev(rho, torch.float64, self.cells), _dev(u, torch.float64, self.D * self.cells),
-            _dev(f, self.storage_dtype, self.Q * self.cells), _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_init_equilibrium(
+                self._h, self._p(rho, torch.float64, self.cells), self._p(u, torch.float64, self.D * self.cells),
+                self._p(f, self.storage_dtype, self.Q * self.cells), _stream(stream)))
         return f
 
     def step(self, f_in: torch.Tensor, f_out: torch.Tensor, nsteps: int, tau: float, stream=None):
         n = self.Q * self.cells
-        _check(lib.eselbm_step(self._h, _dev(f_in, self.storage_dtype, n), _dev(f_out, self.storage_dtype, n),
-                               int(nsteps), float(tau), _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_step(self._h, self._p(f_in, self.storage_dtype, n), self._p(f_out, self.storage_dtype, n),
+                                   int(nsteps), float(tau), _stream(stream)))
 
     def stats(self, with_H: bool = False, stream=None) -> dict:
         """FP64 diagnostics of the last statistics-enabled step (synchronises
@@ -223,7 +244,8 @@ class Solver:
         E_NONPOSITIVE and ``n_nonpos`` > 0, so that a caller can stop a run
         that has lost positivity; every other failure raises EselbmError."""
         st = Stats()
-        status = lib.eselbm_alpha_stats(self._h, ctypes.byref(st), int(bool(with_H)), _stream(stream))
+        with self._on():
+            status = lib.eselbm_alpha_stats(self._h, ctypes.byref(st), int(bool(with_H)), _stream(stream))
         if status not in (OK, E_NONPOSITIVE):
             _check(status)
         d = st.as_dict()
@@ -233,8 +255,9 @@ class Solver:
     def moments(self, f: torch.Tensor, stream=None):
         rho = torch.empty(self.shape, dtype=torch.float64, device=self.device)
         u = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=self.device)
-        _check(lib.eselbm_moments(self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
-                                  _dev(rho), _dev(u), _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_moments(self._h, self._p(f, self.storage_dtype, self.Q * self.cells),
+                                      self._p(rho), self._p(u), _stream(stream)))
         return rho, u
 
     # ---- adjoint ----------------------------------------------------------
@@ -244,41 +267,46 @@ class Solver:
 
     def adjoint_step(self, f_n, lam_next, lam_n, tau: float, force_grad=None, seed_next=None, stream=None):
         n = self.Q * self.cells
-        _check(lib.eselbm_adjoint_step(
-            self._h, _dev(f_n, self.storage_dtype, n), _dev(lam_next, self.compute_dtype, n),
-            _dev(seed_next, self.compute_dtype, (1 + self.D) * self.cells) if seed_next is not None else _vp(None),
-            _dev(lam_n, self.compute_dtype, n), float(tau),
-            _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
-            _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_adjoint_step(
+                self._h, self._p(f_n, self.storage_dtype, n), self._p(lam_next, self.compute_dtype, n),
+                self._p(seed_next, self.compute_dtype, (1 + self.D) * self.cells) if seed_next is not None else _vp(None),
+                self._p(lam_n, self.compute_dtype, n), float(tau),
+                self._p(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+                _stream(stream)))
 
     def kinetic_loss(self, f, loss=None, lam=None, scale: float = 1.0, stream=None):
-        _check(lib.eselbm_kinetic_loss(
-            self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
-            _dev(loss, torch.float64, 1) if loss is not None else _vp(None),
-            _dev(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
-            float(scale), _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_kinetic_loss(
+                self._h, self._p(f, self.storage_dtype, self.Q * self.cells),
+                self._p(loss, torch.float64, 1) if loss is not None else _vp(None),
+                self._p(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
+                float(scale), _stream(stream)))
 
     def dissipation_loss(self, f, loss=None, lam=None, weight: float = 1.0, force_grad=None, stream=None):
-        _check(lib.eselbm_dissipation_loss(
-            self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
-            _dev(loss, torch.float64, 1) if loss is not None else _vp(None),
-            _dev(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
-            float(weight),
-            _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
-            _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_dissipation_loss(
+                self._h, self._p(f, self.storage_dtype, self.Q * self.cells),
+                self._p(loss, torch.float64, 1) if loss is not None else _vp(None),
+                self._p(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
+                float(weight),
+                self._p(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+                _stream(stream)))
 
     def dissipation_seed(self, f, seed, weight: float = 1.0, force_grad=None, stream=None):
-        _check(lib.eselbm_dissipation_seed(
-            self._h, _dev(f, self.storage_dtype, self.Q * self.cells),
-            _dev(seed, self.compute_dtype, (1 + self.D) * self.cells), float(weight),
-            _dev(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
-            _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_dissipation_seed(
+                self._h, self._p(f, self.storage_dtype, self.Q * self.cells),
+                self._p(seed, self.compute_dtype, (1 + self.D) * self.cells), float(weight),
+                self._p(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+                _stream(stream)))
 
     def equilibrium_vjp(self, rho, u, lam, stream=None) -> torch.Tensor:
         gu = torch.empty((self.D,) + self.shape, dtype=torch.float64, device=self.device)
-        _check(lib.eselbm_equilibrium_vjp(
-            self._h, _dev(rho, torch.float64, self.cells), _dev(u, torch.float64, self.D * self.cells),
-            _dev(lam, self.compute_dtype, self.Q * self.cells), _dev(gu), _stream(stream)))
+        with self._on():
+            _check(lib.eselbm_equilibrium_vjp(
+                self._h, self._p(rho, torch.float64, self.cells), self._p(u, torch.float64, self.D * self.cells),
+                self._p(lam, self.compute_dtype, self.Q * self.cells), self._p(gu), _stream(stream)))
         return gu
 
 
