@@ -152,6 +152,59 @@ def test_tgv2d_64_1000_steps(es, dtype, tols):
     assert abs(st["H"] - ref["H"]) < (1e-12 if dtype == "f64" else 1e-5) * abs(ref["H"])
 
 
+_SHEAR_FULL = {}
+
+
+def _shear_full_oracle(kind):
+    """The oracle over the first 1000 steps of the full 1024^2 shear layer,
+    in FP64 (kind "f64") or with its state rounded to FP32 after every step
+    (kind "f32"), computed once per module in chunks that report progress."""
+    if kind in _SHEAR_FULL:
+        return _SHEAR_FULL[kind]
+    wl = W.SHEAR_1024
+    rho, u = W.fields_for(wl)
+    f = oracle.init_equilibrium(rho, u)
+    if kind == "f32":
+        f = f.astype(np.float32).astype(np.float64)
+    done, chunk = 0, (100 if kind == "f64" else 1)
+    while done < 1000:
+        n = min(chunk, 1000 - done)
+        if done + n == 1000:
+            f, alpha, counts = oracle.step(f, n, wl.tau, want_alpha=True)
+        else:
+            f = oracle.step(f, n, wl.tau)
+        if kind == "f32":
+            f = f.astype(np.float32).astype(np.float64)
+        done += n
+        if done % 100 == 0:
+            _log(f"[oracle shear 1024^2 {kind}] {done} steps")
+    r, v = oracle.moments(f)
+    _SHEAR_FULL[kind] = dict(f=f, rho=r, u=v, alpha=alpha, counts=counts)
+    return _SHEAR_FULL[kind]
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("dtype,tols", [
+    ("f64", (1e-11, 1e-11, 1e-9, 0.0)),
+    ("f32s", (1e-6, 1e-6, 1e-5, 1e-4)),
+    ("f32", (0.0, 0.0, 1e-5, 1e-4)),
+])
+def test_shear_layer_1024_1000_steps(es, dtype, tols):
+    """The 1024^2 shear-layer workload at its full size, in the bench's launch
+    configuration, element by element against the oracle after 1000 steps
+    (a minute or two of host time per oracle run).  Plain F32 is held to 4x
+    the oracle's own error when its state is rounded to FP32 every step."""
+    wl = W.SHEAR_1024
+    rho, u = W.fields_for(wl)
+    _log(f"[shear 1024^2 {dtype}] GPU, 1000 steps")
+    gpu = _gpu_run(es, "D2Q9", rho, u, 1000, wl.tau, dtype)
+    ref = _shear_full_oracle("f64")
+    emul = _shear_full_oracle("f32") if dtype == "f32" else None
+    _compare(gpu, ref, *tols, label=f"shear1024 {dtype}", emul=emul)
+    st = gpu["stats"]
+    assert st["n_nonpos"] == 0 and st["n_cells"] == 1024 * 1024
+
+
 @pytest.mark.parametrize("dtype,tols", [
     ("f64", (1e-11, 1e-11, 1e-9, 0.0)),
     ("f32s", (1e-6, 1e-6, 1e-5, 1e-4)),
