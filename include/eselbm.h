@@ -148,7 +148,8 @@ typedef struct {
 /* Creates a solver for an nx * ny * nz periodic grid (nz must be 1 for
  * D2Q9).  Allocates the accumulator block on the current device.
  * Errors: ESELBM_E_ARG for a NULL out, dims < 1, unknown lattice or dtype;
- * ESELBM_E_UNSUPPORTED for ny or nz above 65535 (the step launches one block
+ * ESELBM_E_UNSUPPORTED for nx above 2^28 (the kernels address a row by a
+ * 32-bit byte offset), ny or nz above 65535 (the step launches one block
  * row per (y, z)) or more than 2^32 - 2^16 cells (the cell-wise passes use a
  * 1-D launch, whose size in work-items is 32-bit; at 4 B per population a
  * D3Q27 lattice of that many cells would already take 464 GB). */

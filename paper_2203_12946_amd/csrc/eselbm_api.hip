@@ -75,6 +75,8 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
     if (nx < 1 || ny < 1 || nz < 1) return fail(ESELBM_E_ARG, "eselbm_create: grid dimensions must be >= 1");
     if (lattice == ESELBM_D2Q9 && nz != 1) return fail(ESELBM_E_ARG, "eselbm_create: D2Q9 needs nz == 1");
     if (ny > 65535 || nz > 65535) return fail(ESELBM_E_UNSUPPORTED, "eselbm_create: ny and nz must be <= 65535");
+    // the kernels address a row by a 32-bit byte offset from its start
+    if (nx > (1 << 28)) return fail(ESELBM_E_UNSUPPORTED, "eselbm_create: nx must be <= 2^28");
     const int Q = lattice == ESELBM_D2Q9 ? 9 : 27;
     const long long N = (long long)nx * ny * nz;
     // the cell-wise passes launch one work-item per cell in a 1-D grid, whose

@@ -57,5 +57,11 @@ def test_argument_errors_without_device(lib):
     assert lib.eselbm_create(ctypes.byref(h), 0, 4, 4, 2, 1) == 1  # D2Q9 with nz != 1
     assert lib.eselbm_create(ctypes.byref(h), 1, 0, 4, 4, 1) == 1
     assert lib.eselbm_create(ctypes.byref(h), 1, 4, 4, 4, 9) == 1
+    # limits of the kernels' addressing, rejected before any device call
+    assert lib.eselbm_create(ctypes.byref(h), 0, (1 << 28) + 1, 1, 1, 0) == 2  # row beyond 32-bit offsets
+    assert b"nx" in lib.eselbm_last_error()
+    assert lib.eselbm_create(ctypes.byref(h), 1, 4, 65536, 4, 1) == 2  # grid y beyond the launch limit
+    assert lib.eselbm_create(ctypes.byref(h), 1, 1 << 17, 1 << 15, 2, 1) == 2  # 2^33 cells
+    assert b"2^32" in lib.eselbm_last_error()
     assert lib.eselbm_step(None, None, None, 1, ctypes.c_double(0.1), None) == 1
     assert lib.eselbm_destroy(None) == 0
