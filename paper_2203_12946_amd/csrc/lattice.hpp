@@ -425,8 +425,15 @@ __device__ __attribute__((always_inline)) inline A alpha_exact(const T (&p)[Lat<
     xmin = A(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const A di = A(d[i]);
-        const A xi = di * rcp_(A(gval<D, T, SH>(i, p)));
+        // the population is read here (the empty asm keeps the compiler from
+        // forming it, or its x, ahead of this iteration), and its terms are
+        // added to the sums before the next population's are formed (the
+        // empty asm at the end pins the sums there): otherwise the terms of
+        // many populations stay live at once and spill to scratch
+        T gi0 = gval<D, T, SH>(i, p), di0 = d[i];
+        asm volatile("" : "+v"(gi0), "+v"(di0));
+        const A di = A(di0);
+        const A xi = di * rcp_(A(gi0));
         xmin = fmin_(xmin, xi);
         const A gx2 = di * xi;  // g x^2
         S2 += gx2;
@@ -443,6 +450,7 @@ __device__ __attribute__((always_inline)) inline A alpha_exact(const T (&p)[Lat<
         const A r = rcp_(q1 * p3);
         C1 += A(2) * gx2 * p3 * r;
         C += gx2 * (A(60) + xi * (A(60) + A(11) * xi)) * q1 * r;
+        asm volatile("" : "+v"(S2), "+v"(M3), "+v"(M4), "+v"(M5), "+v"(M6), "+v"(C1), "+v"(C), "+v"(xmin));
         // one population at a time: interleaving the unrolled iterations
         // would hold more temporaries than the register budget
         __builtin_amdgcn_sched_barrier(0);

@@ -313,8 +313,43 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
     constexpr int Q = Lat<D>::Q;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const long long N = a.g.N;
-    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
-    const int x = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+    // this lane's cell: in the periodic kernel, of the launch's box (lanes
+    // along x, one block row per (y, z)); in the walled kernel, of the shell
+    // pieces, found by the lane's 1-D index (constant piece indices, so that
+    // the piece table stays in kernel arguments)
+    int x, y, z;
+    bool in;
+    if constexpr (WALL) {
+        unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
+        int o[3] = {0, 0, 0}, f = 0, m = 1;
+        unsigned e = 1;
+        in = false;
+#pragma unroll
+        for (int sg = 0; sg < 6; ++sg) {
+            if (in || sg >= a.nseg) continue;
+            if (k < a.seg_n[sg]) {
+                in = true;
+                o[0] = a.seg_o[sg][0];
+                o[1] = a.seg_o[sg][1];
+                o[2] = a.seg_o[sg][2];
+                f = a.seg_f[sg];
+                m = a.seg_m[sg];
+                e = (unsigned)a.seg_e[sg];
+            } else {
+                k -= a.seg_n[sg];
+            }
+        }
+        const int fast = (int)(k % e), mid = (int)(k / e);
+        x = o[0] + (f == 0 ? fast : 0) + (m == 0 ? mid : 0);
+        y = o[1] + (f == 1 ? fast : 0) + (m == 1 ? mid : 0);
+        z = o[2] + (f == 2 ? fast : 0) + (m == 2 ? mid : 0);
+    } else {
+        const int lane = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
+        x = a.x0 + lane;
+        y = a.y0 + (int)blockIdx.y;
+        z = a.z0 + (int)blockIdx.z;
+        in = lane < a.ex;
+    }
     // in place the two pointers are the same buffer: no restrict there
     using InP = typename std::conditional<AA == kTwoLattice, const S *__restrict__, const S *>::type;
     using OutP = typename std::conditional<AA == kTwoLattice, S *__restrict__, S *>::type;
@@ -323,7 +358,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
     const T beta = (T)a.beta;
 
     LaneStats ls;
-    if (x < nx) {
+    if (in) {
         // source coordinate of a population with velocity component c is
         // (coordinate - c) mod n, indexed here by c + 1
         const unsigned xs[3] = {x + 1 == nx ? 0u : (unsigned)x + 1u, (unsigned)x,
@@ -473,16 +508,88 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
             }
         }
     }
-    if (DIAG && a.stats) block_reduce_stats(ls, a.stats + (blockIdx.y + blockIdx.z) % kStatSlots);
+    if (DIAG && a.stats) block_reduce_stats(ls, a.stats + (WALL ? blockIdx.x : blockIdx.y + blockIdx.z) % kStatSlots);
+}
+
+// A grid with walls: the cells whose every source lies inside the domain
+// (all but the first and last layer along each walled axis) take the
+// periodic kernel over that box, which then never wraps on a walled axis;
+// the shell of boundary layers takes the walled pull in one launch: the
+// walled z planes, then the walled y rows between them, then the walled x
+// lines between those (along y).  Every cell is updated once.
+template <int D, typename S, int MODE, bool DIAG>
+static hipError_t launch_walled(const StepArgs &a, hipStream_t s)
+{
+    const int n[3] = {a.g.nx, a.g.ny, a.g.nz};
+    int lo[3], hi[3];
+    bool w[3];
+    for (int k = 0; k < 3; ++k) {
+        w[k] = k < D && (a.walls >> k & 1);
+        lo[k] = w[k] ? 1 : 0;
+        hi[k] = w[k] ? n[k] - 1 : n[k];
+        if (hi[k] < lo[k]) hi[k] = lo[k];
+    }
+    StepArgs b = a;
+    b.x0 = lo[0];
+    b.y0 = lo[1];
+    b.z0 = lo[2];
+    b.ex = hi[0] - lo[0];
+    b.ey = hi[1] - lo[1];
+    b.ez = hi[2] - lo[2];
+    if (b.ex > 0 && b.ey > 0 && b.ez > 0) {
+        const int bx = block_x(b.ex);
+        const dim3 grid((unsigned)((b.ex + bx - 1) / bx), (unsigned)b.ey, (unsigned)b.ez), block(bx);
+        hipLaunchKernelGGL((k_step<D, S, MODE, DIAG, false, false>), grid, block, 0, s, b);
+    }
+    b.nseg = 0;
+    long long total = 0;
+    auto piece = [&](int x0, int y0, int z0, int f, int ef, int m, int em) {
+        if (ef <= 0 || em <= 0) return;
+        const int sg = b.nseg++;
+        b.seg_o[sg][0] = x0;
+        b.seg_o[sg][1] = y0;
+        b.seg_o[sg][2] = z0;
+        b.seg_f[sg] = f;
+        b.seg_e[sg] = ef;
+        b.seg_m[sg] = m;
+        b.seg_n[sg] = (unsigned)((long long)ef * em);
+        total += (long long)ef * em;
+    };
+    if (w[2]) {
+        piece(0, 0, 0, 0, n[0], 1, n[1]);
+        if (n[2] > 1) piece(0, 0, n[2] - 1, 0, n[0], 1, n[1]);
+    }
+    if (w[1]) {
+        piece(0, 0, lo[2], 0, n[0], 2, hi[2] - lo[2]);
+        if (n[1] > 1) piece(0, n[1] - 1, lo[2], 0, n[0], 2, hi[2] - lo[2]);
+    }
+    if (w[0]) {
+        piece(0, lo[1], lo[2], 1, hi[1] - lo[1], 2, hi[2] - lo[2]);
+        if (n[0] > 1) piece(n[0] - 1, lo[1], lo[2], 1, hi[1] - lo[1], 2, hi[2] - lo[2]);
+    }
+    // the shell is part of the grid, whose cell count the API keeps below 2^32
+    if (total > 0xFFFFFFFFLL) return hipErrorInvalidValue;
+    if (total > 0) {
+        const unsigned blocks = (unsigned)((total + 255) / 256);
+        hipLaunchKernelGGL((k_step<D, S, MODE, DIAG, false, true>), dim3(blocks), dim3(256), 0, s, b);
+    }
+    return hipGetLastError();
 }
 
 template <int D, typename S, int MODE>
-static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
+static hipError_t launch_step_t(bool diag, const StepArgs &a_in, hipStream_t s)
 {
     // (x-block, y, z); the API limits ny and nz to the grid's 65535
-    const int bx = block_x(a.g.nx);
-    if (a.g.ny > 65535 || a.g.nz > 65535) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)((a.g.nx + bx - 1) / bx), (unsigned)a.g.ny, (unsigned)a.g.nz), block(bx);
+    const int bx = block_x(a_in.g.nx);
+    if (a_in.g.ny > 65535 || a_in.g.nz > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)((a_in.g.nx + bx - 1) / bx), (unsigned)a_in.g.ny, (unsigned)a_in.g.nz), block(bx);
+    // every launch below but the walled ones covers the whole grid
+    StepArgs a = a_in;
+    a.x0 = a.y0 = a.z0 = 0;
+    a.ex = a.g.nx;
+    a.ey = a.g.ny;
+    a.ez = a.g.nz;
+    a.nseg = 0;
     const bool force = a.force != nullptr;
     if (a.aa != kTwoLattice) {
         // in place: periodic, the closed-form and alpha = 2 modes
@@ -521,9 +628,7 @@ static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
     }
     if (a.walls) {
         if (force) return hipErrorInvalidValue;
-        if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, false, true>), grid, block, 0, s, a);
-        else hipLaunchKernelGGL((k_step<D, S, MODE, false, false, true>), grid, block, 0, s, a);
-        return hipGetLastError();
+        return diag ? launch_walled<D, S, MODE, true>(a, s) : launch_walled<D, S, MODE, false>(a, s);
     }
     if (force) {
         if constexpr (std::is_same<S, float>::value) {
