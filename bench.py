@@ -135,6 +135,46 @@ def time_forward(es, torch, W, wl, dtype: str, mode: str, steps: int, warmup: in
                 kernel_ms=kernel_ms, stats=st)
 
 
+def time_cavity(es, torch, W, lattice: str, n: int, dtype: str, re: float, steps: int, warmup: int):
+    """Lid-driven cavity (walls on every axis, the high-y wall moving along x
+    at 0.05), started from rest; timed after the warm-up steps have set the
+    flow going.  Walled grids run the periodic kernel on the interior and the
+    walled pull on the boundary shell."""
+    D = 2 if lattice == "D2Q9" else 3
+    shape = (n,) * D
+    lid = 0.05
+    tau = W.tau_from_nu(lid * n / re)
+    s = es.Solver(lattice, shape, dtype=dtype, mode="higher")
+    s.set_walls([True] * D, {(1, 1): (lid, 0.0, 0.0)[:D]})
+    a = s.init_equilibrium(torch.ones(shape, dtype=torch.float64, device="cuda"),
+                           torch.zeros((D,) + shape, dtype=torch.float64, device="cuda"))
+    b = s.empty_state()
+    s.step(a, b, warmup, tau)  # the newest state lands in b
+    a, b = b, a
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        s.step(a, b, 1, tau)
+        a, b = b, a
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    s.set_stats(True)
+    s.step(a, b, 1, tau)
+    st = s.stats()
+    cells = n ** D
+    bpc = 2 * (9 if D == 2 else 27) * {"f32": 4, "f64": 8}[dtype]
+    gbs = bpc * cells / (ms * 1e-3) / 1e9
+    del a, b, s
+    torch.cuda.empty_cache()
+    return dict(mlups=round(cells / ms / 1e3, 1), kernel_ms=round(ms, 4), hbm_gbs=round(gbs, 1),
+                frac=round(gbs / HBM_PEAK_GBS, 4), bytes_per_cell=bpc, re=re, warmup_steps=warmup,
+                n_gated=st["n_gated"], n_exact=st["n_exact"], n_guard=st["n_guard"])
+
+
 def time_big_in_place(es, torch, W, n: int, steps: int):
     """In-place steps of an n^3 D3Q27 FP32 lattice (one lattice of
     27 * 4 * n^3 bytes), fields built on the device."""
@@ -400,6 +440,13 @@ def main():
             variants[f"{wl2.name}_{dtype}"] = dict(mlups=round(r["mlups"], 1), kernel_ms=round(r["kernel_ms"], 4),
                                                   n_gated=r["stats"]["n_gated"], n_exact=r["stats"]["n_exact"])
         del r2, v2
+        # walls: lid-driven cavities (the boundary rule of Sec. V C)
+        for lattice, n, dtype, re in (("D3Q27", 256, "f32", 1000.0), ("D3Q27", 256, "f64", 1000.0),
+                                      ("D2Q9", 4096, "f32", 5000.0)):
+            name = f"{lattice.lower()}_cavity_{n}_{dtype}"
+            _log(f"bench: {name}")
+            variants[name] = time_cavity(es, torch, W, lattice, n, dtype, re, 100 if lattice == "D3Q27" else 200, 500)
+            _log(f"bench: {name} {variants[name]['mlups']:.0f} MLUPS")
 
     adj = None
     if not args.no_adjoint:

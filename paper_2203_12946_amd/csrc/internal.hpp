@@ -38,16 +38,6 @@ struct StepArgs {
     DevStats *stats;     // kStatSlots slots or null
     double cpr;          // ES-BGK stress factor c_Pr; 0: the equilibrium itself
     int aa;              // 0: two lattices (fin -> fout); in place: 1 the pull half, 2 the local half
-    // The cells one launch updates (set by the launcher).  The periodic
-    // kernel: the box [x0, x0 + ex) x [y0, y0 + ey) x [z0, z0 + ez), lanes
-    // along x, one block row per (y, z).  The walled kernel: nseg pieces of
-    // the boundary shell in one 1-D launch, one work-item per cell; piece s
-    // holds seg_n[s] cells from the corner seg_o[s], along axis seg_f[s]
-    // first (seg_e[s] cells) and then along axis seg_m[s].
-    int x0, y0, z0, ex, ey, ez;
-    int nseg;
-    int seg_o[6][3], seg_f[6], seg_m[6], seg_e[6];
-    unsigned seg_n[6];
 };
 
 // Launchers (return the hipError_t of the launch).

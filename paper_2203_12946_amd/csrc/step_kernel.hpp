@@ -205,10 +205,12 @@ constexpr int step_waves_qe()
     return QE ? ((StepPolicy<S>::eq_f64 || D == 3) ? 1 : 2) : step_waves<S, MODE>();
 }
 
-// The walled pull keeps its per-population wall decisions and the wall
-// node's mass balance live beside the two Q-arrays: two waves per SIMD for
-// D2Q9 in single precision, one for D3Q27 or in double, which removes the
-// spills the periodic step's occupancy floor would force on it.
+// The walled step runs the periodic pull in all but the boundary layers, so
+// it takes the periodic step's occupancy floor, at most three waves per SIMD
+// (the wall node's mass balance adds live values; the closed-form modes then
+// still fit four waves in FP32 and F16 without scratch).  The mirror-condition
+// modes, whose Newton loop already holds two waves' registers, run their
+// walled step at one.
 //
 // The forced step evaluates two more equilibria (at u and u + F/rho) while d
 // and the stored values are live: at the periodic step's four waves its
@@ -216,7 +218,7 @@ constexpr int step_waves_qe()
 template <int D, typename S, int MODE, bool WALL, bool QE, bool FORCE>
 constexpr int step_waves_k()
 {
-    return WALL ? ((D == 3 || StepPolicy<S>::eq_f64) ? 1 : 2)
+    return WALL ? (is_mirror_mode(MODE) ? 1 : (step_waves_qe<D, S, MODE, QE>() > 3 ? 3 : step_waves_qe<D, S, MODE, QE>()))
                 : (FORCE && step_waves_qe<D, S, MODE, QE>() > 3 ? 3 : step_waves_qe<D, S, MODE, QE>());
 }
 
@@ -294,6 +296,43 @@ __device__ inline void pull_walls(const StepArgs &a, int x, int y, int z, typena
     }
 }
 
+// The same rule for a cell whose only sources outside the domain lie across
+// one x wall (SIDE 0: the cell at x = 0, whose populations with c_x = +1
+// come from the wall; SIDE 1: x = nx - 1, c_x = -1), in a row that is
+// interior along y and z, after the periodic pull has loaded every
+// population: those populations are replaced, with the same sums in the same
+// order as pull_walls forms them, so the result is the same to the bit.  The
+// population set is fixed at compile time, so the loads issue together.
+template <int D, typename S, int SIDE>
+__device__ inline void fix_x_wall(const StepArgs &a, long long cell, typename Storage<S>::T (&p)[Lat<D>::Q])
+{
+    using T = typename Storage<S>::T;
+    constexpr int Q = Lat<D>::Q;
+    constexpr bool SH = Storage<S>::kShifted;
+    constexpr int CS = SIDE == 0 ? 1 : -1;
+    const long long N = a.g.N;
+    const S *__restrict__ fin = (const S *)a.fin;
+    using E = typename std::conditional<StepPolicy<S>::mom_f64, double, T>::type;
+    E out_dev = E(0), in_dev = E(0), in_w = E(0);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (Lat<D>::c(i, 0) != CS) continue;
+        in_dev += E(a.wall_eq[SIDE * Q + i]);
+        in_w += E(Lat<D>::w(i));
+        const int j = Q - 1 - i;
+        const E v = E(Storage<S>::to_T(fin[(long long)j * N + cell]));
+        out_dev += SH ? v : v - E(Lat<D>::w(j));
+    }
+    const E drw = (out_dev - in_dev) * rcp_(in_w + in_dev);
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        if (Lat<D>::c(i, 0) != CS) continue;
+        const E e = E(a.wall_eq[SIDE * Q + i]);
+        const E dev = fma_(drw, E(Lat<D>::w(i)) + e, e);
+        p[i] = SH ? T(dev) : T(E(Lat<D>::w(i)) + dev);
+    }
+}
+
 // In-place (AA) stepping on one lattice: pairs of launches, the first of
 // which reads every population from its source cell x - c_i (as the
 // two-lattice pull) and writes the post-collision population i back to the
@@ -313,43 +352,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
     constexpr int Q = Lat<D>::Q;
     const int nx = a.g.nx, ny = a.g.ny, nz = a.g.nz;
     const long long N = a.g.N;
-    // this lane's cell: in the periodic kernel, of the launch's box (lanes
-    // along x, one block row per (y, z)); in the walled kernel, of the shell
-    // pieces, found by the lane's 1-D index (constant piece indices, so that
-    // the piece table stays in kernel arguments)
-    int x, y, z;
-    bool in;
-    if constexpr (WALL) {
-        unsigned k = blockIdx.x * blockDim.x + threadIdx.x;
-        int o[3] = {0, 0, 0}, f = 0, m = 1;
-        unsigned e = 1;
-        in = false;
-#pragma unroll
-        for (int sg = 0; sg < 6; ++sg) {
-            if (in || sg >= a.nseg) continue;
-            if (k < a.seg_n[sg]) {
-                in = true;
-                o[0] = a.seg_o[sg][0];
-                o[1] = a.seg_o[sg][1];
-                o[2] = a.seg_o[sg][2];
-                f = a.seg_f[sg];
-                m = a.seg_m[sg];
-                e = (unsigned)a.seg_e[sg];
-            } else {
-                k -= a.seg_n[sg];
-            }
-        }
-        const int fast = (int)(k % e), mid = (int)(k / e);
-        x = o[0] + (f == 0 ? fast : 0) + (m == 0 ? mid : 0);
-        y = o[1] + (f == 1 ? fast : 0) + (m == 1 ? mid : 0);
-        z = o[2] + (f == 2 ? fast : 0) + (m == 2 ? mid : 0);
-    } else {
-        const int lane = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
-        x = a.x0 + lane;
-        y = a.y0 + (int)blockIdx.y;
-        z = a.z0 + (int)blockIdx.z;
-        in = lane < a.ex;
-    }
+    const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+    const int x = (int)blockIdx.x * (int)blockDim.x + (int)threadIdx.x;
     // in place the two pointers are the same buffer: no restrict there
     using InP = typename std::conditional<AA == kTwoLattice, const S *__restrict__, const S *>::type;
     using OutP = typename std::conditional<AA == kTwoLattice, S *__restrict__, S *>::type;
@@ -358,7 +362,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
     const T beta = (T)a.beta;
 
     LaneStats ls;
-    if (in) {
+    if (x < nx) {
         // source coordinate of a population with velocity component c is
         // (coordinate - c) mod n, indexed here by c + 1
         const unsigned xs[3] = {x + 1 == nx ? 0u : (unsigned)x + 1u, (unsigned)x,
@@ -376,18 +380,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
         // varies per lane.
         constexpr bool SH = Storage<S>::kShifted;
         T p[Q];
-        if constexpr (WALL) {
-            pull_walls<D, S>(a, x, y, z, p);
-        } else if constexpr (AA == kAALocal) {
-#pragma unroll
-            for (int i = 0; i < Q; ++i) p[i] = Storage<S>::to_T(fin[(long long)(Q - 1 - i) * N + cell]);
-        } else {
+        auto pull = [&]() {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 const int cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1, cx = Lat<D>::c(i, 0) + 1;
                 const S *rowp = fin + ((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
                 p[i] = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
             }
+        };
+        if constexpr (WALL) {
+            // A row in the first or last layer along a walled y or z axis
+            // (block-uniform) takes the walled pull throughout.  Every other
+            // row pulls as in the periodic step, with the row's coalesced
+            // loads, and only its cells at a walled x boundary then replace
+            // the populations whose source lies beyond it.
+            // (A row one cell long between x walls has both at one cell.)
+            const bool wall_row = ((a.walls & 2) && (y == 0 || y == ny - 1)) ||
+                                  (D == 3 && (a.walls & 4) && (z == 0 || z == nz - 1)) ||
+                                  ((a.walls & 1) && nx == 1);
+            if (wall_row) {
+                pull_walls<D, S>(a, x, y, z, p);
+            } else {
+                pull();
+                if (a.walls & 1) {
+                    if (x == 0) fix_x_wall<D, S, 0>(a, cell, p);
+                    else if (x == nx - 1) fix_x_wall<D, S, 1>(a, cell, p);
+                }
+            }
+        } else if constexpr (AA == kAALocal) {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) p[i] = Storage<S>::to_T(fin[(long long)(Q - 1 - i) * N + cell]);
+        } else {
+            pull();
         }
         auto dev = [&](int i) { return SH ? p[i] : p[i] - T(Lat<D>::w(i)); };
 
@@ -508,88 +532,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
             }
         }
     }
-    if (DIAG && a.stats) block_reduce_stats(ls, a.stats + (WALL ? blockIdx.x : blockIdx.y + blockIdx.z) % kStatSlots);
-}
-
-// A grid with walls: the cells whose every source lies inside the domain
-// (all but the first and last layer along each walled axis) take the
-// periodic kernel over that box, which then never wraps on a walled axis;
-// the shell of boundary layers takes the walled pull in one launch: the
-// walled z planes, then the walled y rows between them, then the walled x
-// lines between those (along y).  Every cell is updated once.
-template <int D, typename S, int MODE, bool DIAG>
-static hipError_t launch_walled(const StepArgs &a, hipStream_t s)
-{
-    const int n[3] = {a.g.nx, a.g.ny, a.g.nz};
-    int lo[3], hi[3];
-    bool w[3];
-    for (int k = 0; k < 3; ++k) {
-        w[k] = k < D && (a.walls >> k & 1);
-        lo[k] = w[k] ? 1 : 0;
-        hi[k] = w[k] ? n[k] - 1 : n[k];
-        if (hi[k] < lo[k]) hi[k] = lo[k];
-    }
-    StepArgs b = a;
-    b.x0 = lo[0];
-    b.y0 = lo[1];
-    b.z0 = lo[2];
-    b.ex = hi[0] - lo[0];
-    b.ey = hi[1] - lo[1];
-    b.ez = hi[2] - lo[2];
-    if (b.ex > 0 && b.ey > 0 && b.ez > 0) {
-        const int bx = block_x(b.ex);
-        const dim3 grid((unsigned)((b.ex + bx - 1) / bx), (unsigned)b.ey, (unsigned)b.ez), block(bx);
-        hipLaunchKernelGGL((k_step<D, S, MODE, DIAG, false, false>), grid, block, 0, s, b);
-    }
-    b.nseg = 0;
-    long long total = 0;
-    auto piece = [&](int x0, int y0, int z0, int f, int ef, int m, int em) {
-        if (ef <= 0 || em <= 0) return;
-        const int sg = b.nseg++;
-        b.seg_o[sg][0] = x0;
-        b.seg_o[sg][1] = y0;
-        b.seg_o[sg][2] = z0;
-        b.seg_f[sg] = f;
-        b.seg_e[sg] = ef;
-        b.seg_m[sg] = m;
-        b.seg_n[sg] = (unsigned)((long long)ef * em);
-        total += (long long)ef * em;
-    };
-    if (w[2]) {
-        piece(0, 0, 0, 0, n[0], 1, n[1]);
-        if (n[2] > 1) piece(0, 0, n[2] - 1, 0, n[0], 1, n[1]);
-    }
-    if (w[1]) {
-        piece(0, 0, lo[2], 0, n[0], 2, hi[2] - lo[2]);
-        if (n[1] > 1) piece(0, n[1] - 1, lo[2], 0, n[0], 2, hi[2] - lo[2]);
-    }
-    if (w[0]) {
-        piece(0, lo[1], lo[2], 1, hi[1] - lo[1], 2, hi[2] - lo[2]);
-        if (n[0] > 1) piece(n[0] - 1, lo[1], lo[2], 1, hi[1] - lo[1], 2, hi[2] - lo[2]);
-    }
-    // the shell is part of the grid, whose cell count the API keeps below 2^32
-    if (total > 0xFFFFFFFFLL) return hipErrorInvalidValue;
-    if (total > 0) {
-        const unsigned blocks = (unsigned)((total + 255) / 256);
-        hipLaunchKernelGGL((k_step<D, S, MODE, DIAG, false, true>), dim3(blocks), dim3(256), 0, s, b);
-    }
-    return hipGetLastError();
+    if (DIAG && a.stats) block_reduce_stats(ls, a.stats + (blockIdx.y + blockIdx.z) % kStatSlots);
 }
 
 template <int D, typename S, int MODE>
-static hipError_t launch_step_t(bool diag, const StepArgs &a_in, hipStream_t s)
+static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
 {
     // (x-block, y, z); the API limits ny and nz to the grid's 65535
-    const int bx = block_x(a_in.g.nx);
-    if (a_in.g.ny > 65535 || a_in.g.nz > 65535) return hipErrorInvalidConfiguration;
-    const dim3 grid((unsigned)((a_in.g.nx + bx - 1) / bx), (unsigned)a_in.g.ny, (unsigned)a_in.g.nz), block(bx);
-    // every launch below but the walled ones covers the whole grid
-    StepArgs a = a_in;
-    a.x0 = a.y0 = a.z0 = 0;
-    a.ex = a.g.nx;
-    a.ey = a.g.ny;
-    a.ez = a.g.nz;
-    a.nseg = 0;
+    const int bx = block_x(a.g.nx);
+    if (a.g.ny > 65535 || a.g.nz > 65535) return hipErrorInvalidConfiguration;
+    const dim3 grid((unsigned)((a.g.nx + bx - 1) / bx), (unsigned)a.g.ny, (unsigned)a.g.nz), block(bx);
     const bool force = a.force != nullptr;
     if (a.aa != kTwoLattice) {
         // in place: periodic, the closed-form and alpha = 2 modes
@@ -628,7 +580,9 @@ static hipError_t launch_step_t(bool diag, const StepArgs &a_in, hipStream_t s)
     }
     if (a.walls) {
         if (force) return hipErrorInvalidValue;
-        return diag ? launch_walled<D, S, MODE, true>(a, s) : launch_walled<D, S, MODE, false>(a, s);
+        if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, false, true>), grid, block, 0, s, a);
+        else hipLaunchKernelGGL((k_step<D, S, MODE, false, false, true>), grid, block, 0, s, a);
+        return hipGetLastError();
     }
     if (force) {
         if constexpr (std::is_same<S, float>::value) {

@@ -157,10 +157,11 @@ class Solver:
         self.set_mode(mode)
 
     def __del__(self):
-        h = getattr(self, "_h", None)
-        if h is not None and h.value and getattr(self, "_lib", None) is not None:
-            self._lib.eselbm_destroy(h)
-            self._h = _vp()
+        # no module globals here: at interpreter exit they may already be gone
+        h, lib = getattr(self, "_h", None), getattr(self, "_lib", None)
+        self._h = None
+        if h is not None and h.value and lib is not None:
+            lib.eselbm_destroy(h)
 
     def _p(self, t, dtype=None, numel=None) -> _vp:
         return _dev(t, dtype, numel, self.device)

@@ -126,12 +126,13 @@ def test_cavity_parity(es, D, shape, mode, dtype):
     (3, (2, 9, 5), [False, False, True]),
     (3, (3, 1, 66), [True, True, True]),
 ])
-def test_interior_and_shell_cover_the_grid(es, D, shape, walls):
-    """A walled grid runs as the periodic kernel on the cells whose sources
-    all lie inside the domain and the walled kernel on the boundary shell
-    (z planes, y rows, x lines along y).  Every cell must be updated exactly
-    once by the right kernel: FP64 against the oracle, a few steps from a
-    rough state, on grids where that split is ragged or degenerate."""
+def test_wall_rows_and_x_boundaries(es, D, shape, walls):
+    """The walled step takes the general walled pull in the rows of the first
+    and last layers along walled y and z axes, the periodic pull elsewhere,
+    and, at a walled x boundary of those rows, replaces only the populations
+    whose source lies beyond it.  FP64 against the oracle, a few steps from a
+    rough state, on grids where those cases are ragged or degenerate (several
+    blocks per row, axes one or two cells wide, partial wall masks)."""
     tau, n = 0.02, 4
     vel = {(1, 1): (0.08, 0.0, 0.0)[:D]} if walls[1] else {}
     f0 = _cavity_state(D, shape, 11 + sum(shape))
@@ -140,7 +141,7 @@ def test_interior_and_shell_cover_the_grid(es, D, shape, walls):
     f_ref = oracle.step_walls(_round(f0, None), n, tau, walls, vel, mode="higher")
     df = float(np.max(np.abs(g["f"] - f_ref)))
     da = float(np.max(np.abs(g["alpha"] - ref["alpha"])))
-    _log(f"[walls split {D}D {shape} {walls}] max|df|={df:.2e} max|dalpha|={da:.2e}")
+    _log(f"[wall rows {D}D {shape} {walls}] max|df|={df:.2e} max|dalpha|={da:.2e}")
     assert df <= 1e-14 and da <= 1e-9
     assert g["stats"]["n_cells"] == int(np.prod(shape))
     assert g["stats"]["n_nonpos"] == 0
