@@ -131,8 +131,8 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
 //    arithmetic rounding; F64: every part is double already.
 // The kernel is a stream of Q loads and Q stores per lane and needs several
 // waves per SIMD in flight to cover HBM latency: 4 waves (<= 128 VGPRs) for
-// the single-precision step, 3 where double moments and equilibrium need the
-// registers.
+// the 4- and 2-byte formats; the double moments and equilibrium of
+// F32-shifted fit there too without scratch on the common path.
 template <typename S>
 struct StepPolicy {
     static constexpr int waves = 4;
@@ -141,7 +141,7 @@ struct StepPolicy {
 };
 template <>
 struct StepPolicy<f32s> {
-    static constexpr int waves = 3;
+    static constexpr int waves = 4;
     static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = true;
     using Exact = double;
 };
