@@ -307,10 +307,16 @@ def cpu_baseline(W, wl, seconds_target: float = 15.0):
 
     def timed(nz, budget):
         f0 = oracle.init_equilibrium(rho[:nz].copy(), u[:, :nz].copy())
+        # per-step time without the call's fixed cost (thread start-up, the
+        # allocation and first touch of its buffers): one step against three
+        oracle.step(f0, 1, wl.tau)
         t0 = time.perf_counter()
         oracle.step(f0, 1, wl.tau)
-        per_step = time.perf_counter() - t0
-        nsteps = max(1, min(1000, int(budget / max(per_step, 1e-3))))
+        t1 = time.perf_counter()
+        oracle.step(f0, 3, wl.tau)
+        t3 = time.perf_counter() - t1
+        per_step = max((t3 - (t1 - t0)) / 2, 1e-4)
+        nsteps = max(1, min(1000, int(budget / per_step)))
         t0 = time.perf_counter()
         oracle.step(f0, nsteps, wl.tau)
         dt = time.perf_counter() - t0
