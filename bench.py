@@ -356,8 +356,8 @@ def main():
     ap.add_argument("--adjoint-steps", type=int, default=500)
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py: this build runs on one GPU; multi-GPU runs (domain decomposition) "
-              "are not part of it", file=sys.stderr)
+        print(f"bench.py: --gpus {args.gpus}: the library steps one GPU's lattice; a run over several GPUs "
+              "(z-slab domain decomposition with halo exchange) is not implemented", file=sys.stderr)
         sys.exit(2)
 
     import torch
