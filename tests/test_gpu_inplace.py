@@ -37,7 +37,12 @@ def _upload(s, f, dtype):
 
 
 @pytest.mark.parametrize("mode", ["higher", "lower", "bgk", "lbgk"])
-@pytest.mark.parametrize("D,shape", [(2, (20, 70)), (3, (6, 9, 70))])
+@pytest.mark.parametrize("D,shape", [(2, (20, 70)), (3, (6, 9, 70)),
+                                     # rows of several blocks with a ragged tail, a row of exactly
+                                     # one full block, rows one and two cells long: every case of
+                                     # the pull half's shifted stores at block and row edges
+                                     (2, (5, 300)), (3, (3, 4, 260)), (3, (2, 3, 256)), (2, (7, 1)),
+                                     (2, (4, 2))])
 @pytest.mark.parametrize("dtype", ["f64", "f32", "f32s", "f16s"])
 def test_in_place_equals_two_lattices(es, D, shape, mode, dtype):
     lat = "D2Q9" if D == 2 else "D3Q27"
@@ -57,7 +62,10 @@ def test_in_place_equals_two_lattices(es, D, shape, mode, dtype):
     s.step(c, c, n, tau)
     st1 = s.stats()
     torch.cuda.synchronize()
-    same = torch.equal(b, c) and torch.equal(alpha1, alpha2)
+    # alpha is NaN in a cell left uncollided (non-positive populations, which
+    # plain BGK can produce on these rough states): compare NaN for NaN
+    same = (torch.equal(b, c) and torch.equal(torch.isnan(alpha1), torch.isnan(alpha2))
+            and torch.equal(torch.nan_to_num(alpha1, nan=0.0), torch.nan_to_num(alpha2, nan=0.0)))
     _log(f"[in place {lat} {dtype} {mode}] identical to two lattices: {same}; "
          f"gated {st1['n_gated']}/{st2['n_gated']}, exact {st1['n_exact']}/{st2['n_exact']}")
     assert same
