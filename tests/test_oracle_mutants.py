@@ -16,8 +16,12 @@ import pytest
 ROOT = pathlib.Path(__file__).resolve().parents[1]
 SRC = ROOT / "oracle" / "eselbm_oracle.c"
 
-# (name, original text, mutated text): the original must occur in the source;
-# the first occurrence is replaced.
+SUITES = ("tests/test_oracle_pins.py", "tests/test_oracle_adjoint_ref.py")
+PINS_ONLY = ("tests/test_oracle_pins.py",)
+
+# (name, original text, mutated text[, suites]): the original must occur in
+# the source; the first occurrence is replaced.  The suites default to both
+# pin files.
 MUTANTS = [
     ("weights", "return c == 0 ? 2.0 / 3.0 : 1.0 / 6.0;", "return c == 0 ? 1.0 / 2.0 : 1.0 / 4.0;"),
     ("equilibrium z", "z[a] = (2.0 * u[a] + s) / (1.0 - u[a]);", "z[a] = (2.0 * u[a] + s) / (1.0 + u[a]);"),
@@ -39,7 +43,13 @@ MUTANTS = [
     ("relaxation", "nxt[(long long)i * N + cell] = g[i] + alpha * beta * (feq[i] - g[i]);",
      "nxt[(long long)i * N + cell] = g[i] + alpha * (feq[i] - g[i]);"),
     ("streaming direction", "long long sx = wrap(xx - c[3 * i + 0], nx);", "long long sx = wrap(xx + c[3 * i + 0], nx);"),
-    ("force", "uf[a] = u[a] + force[(long long)a * N + cell] / rho;", "uf[a] = u[a] + force[(long long)a * N + cell];"),
+    # the forcing term has no counterpart in the paper: its mutants must be
+    # caught by the moment pins alone, not by the torch reference (the same
+    # reading written a second time)
+    ("force", "uf[a] = u[a] + force[(long long)a * N + cell] / rho;", "uf[a] = u[a] + force[(long long)a * N + cell];",
+     PINS_ONLY),
+    ("force sign", "nxt[(long long)i * N + cell] += feqf[i] - feq[i];", "nxt[(long long)i * N + cell] += feq[i] - feqf[i];",
+     PINS_ONLY),
     ("H", "part += v * (log(v / w[i]) - 1.0);", "part += v * log(v);"),
     ("Delta H", "s2 += g[i] * x * log1p(x);", "s2 += g[i] * x * x;"),
     ("alpha_Iterate1", "return a0 - orc_dH_mirror(Q, g, feq, a0) / dH_mirror_prime(Q, g, x, a0);",
@@ -53,7 +63,8 @@ MUTANTS = [
 
 
 def _run(case, tmp):
-    name, orig, mut = case
+    name, orig, mut = case[:3]
+    suites = case[3] if len(case) > 3 else SUITES
     src = SRC.read_text()
     if orig not in src:
         return name, None, "mutation site not found"
@@ -65,7 +76,7 @@ def _run(case, tmp):
     subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", str(lib), str(bad), "-lm"])
     env = dict(os.environ, ESELBM_ORACLE_LIB=str(lib), OMP_NUM_THREADS="1")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-m", "not gpu", "-p", "no:cacheprovider",
-                        "tests/test_oracle_pins.py", "tests/test_oracle_adjoint_ref.py"],
+                        *suites],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=900)
     caught = [ln.split(" ")[1] for ln in r.stdout.splitlines() if ln.startswith("FAILED ")]
     return name, r.returncode, caught[0] if caught else r.stdout[-1500:]

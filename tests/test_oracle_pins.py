@@ -940,3 +940,59 @@ def test_esbgk_lattice_conserves():
             m0 = np.tensordot(c[:, a], f, axes=(0, 0)).sum()
             m1 = np.tensordot(c[:, a], out, axes=(0, 0)).sum()
             assert abs(m1 - m0) < 1e-13
+
+
+# --------------------------------------------------------------------------
+# Body force of the forced workload (the paper has none: an exact-difference
+# term added after the collision is this library's reading)
+# --------------------------------------------------------------------------
+def _pulled(f):
+    """g_i(x) = f_i(x - c_i) on the periodic grid (Eq. advection), by np.roll."""
+    D = f.ndim - 1
+    c, _ = oracle.lattice(D)
+    g = np.empty_like(f)
+    for i in range(c.shape[0]):
+        shift = tuple(int(c[i, a]) for a in reversed(range(D)))
+        g[i] = np.roll(f[i], shift, axis=tuple(range(D)))
+    return g
+
+
+@pytest.mark.parametrize("D", [2, 3])
+def test_force_increment_moments(D):
+    """The forcing increment of one step, Delta = step(F) - step(0) cell by
+    cell, carries exactly the moments a body force must inject, whatever the
+    cell's path length: no mass (sum_i Delta_i = 0), the momentum F
+    (sum_i c_i Delta_i = F), and the change of the equilibrium pressure
+    tensor between u and u + F/rho that the D1Q3 factors fix in closed form:
+    off the diagonal rho u_a u_b is exact, so the change is
+    u_a F_b + u_b F_a + F_a F_b / rho; on it each axis carries
+    rho (2 sqrt(1 + 3 u_a^2) - 1) / 3.  Densities far from 1 make a force
+    applied as F rather than F / rho fail by (rho - 1) F."""
+    rng = np.random.default_rng(11 + D)
+    shape = (6, 7) if D == 2 else (4, 5, 6)
+    rho0 = 1.0 + 0.25 * rng.uniform(-1, 1, shape)
+    u0 = 0.04 * rng.standard_normal((D,) + shape)
+    f = oracle.init_equilibrium(rho0, u0) * (1.0 + 0.01 * rng.uniform(-1, 1, (3 ** D,) + shape))
+    F = 1e-3 * rng.standard_normal((D,) + shape)
+    tau = 3e-3
+    out0, a0, _ = oracle.step(f, 1, tau, want_alpha=True)
+    outF, aF, _ = oracle.step(f, 1, tau, force=F, want_alpha=True)
+    np.testing.assert_array_equal(a0, aF)  # the force does not enter the path length
+    assert np.all(np.abs(a0 - 2.0) > 1e-6)  # every cell off the gate: alpha varies
+    delta = outF - out0
+    c, _ = oracle.lattice(D)
+    c = c[:, :D].astype(float)
+    g = _pulled(f)
+    rho = g.sum(0)
+    u = np.einsum("ia,i...->a...", c, g) / rho
+    assert np.max(np.abs(delta.sum(0))) < 1e-14
+    np.testing.assert_allclose(np.einsum("ia,i...->a...", c, delta), F, rtol=0, atol=1e-14)
+    P = np.einsum("ia,ib,i...->ab...", c, c, delta)
+    uf = u + F / rho
+    for a in range(D):
+        diag = 2.0 * rho / 3.0 * (np.sqrt(1 + 3 * uf[a] ** 2) - np.sqrt(1 + 3 * u[a] ** 2))
+        np.testing.assert_allclose(P[a, a], diag, rtol=0, atol=1e-14)
+        for b in range(D):
+            if b != a:
+                off = u[a] * F[b] + u[b] * F[a] + F[a] * F[b] / rho
+                np.testing.assert_allclose(P[a, b], off, rtol=0, atol=1e-14)
