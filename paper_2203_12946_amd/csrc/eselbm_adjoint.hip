@@ -185,19 +185,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
     T *__restrict__ lout = (T *)a.lam_n;
     const T beta = (T)a.beta;
 
-    const unsigned xs[3] = {x + 1 == nx ? 0u : (unsigned)x + 1u, (unsigned)x,
-                            x == 0 ? (unsigned)nx - 1u : (unsigned)x - 1u};
-    const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
-    const int zs[3] = {z + 1 == nz ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
-    const long long row0 = ((long long)z * ny + y) * nx;
+    const PullIndex<D> pix(x, y, z, nx, ny, nz);
+    const long long row0 = pix.row0;
 
-    // Row starts are block-uniform.  Each access takes its row offset through
-    // an empty asm, so that it is a scalar base plus the lane's 32-bit offset:
-    // otherwise the compiler folds the lane offset into 64-bit per-lane
-    // addresses and keeps all Q of them live between the reads of a row.
-    auto opaque = [](long long o) {
-        asm volatile("" : "+s"(o));
-        return o;
+    // Row starts are block-uniform (they depend on the block's y and z
+    // only).  The adjoint's reads of lambda and its pushes take them through
+    // readfirstlane, one 32-bit half at a time, so that each access is a
+    // scalar base plus the lane's 32-bit offset: otherwise the compiler folds
+    // the lane offset into 64-bit per-lane addresses and keeps all Q of them
+    // live between the accesses of a row.  readfirstlane returns the value
+    // of the first active lane, the same in every lane here.
+    auto uniform = [](long long o) {
+        const unsigned long long u = (unsigned long long)o;
+        const unsigned lo = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)u);
+        const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
+        return (long long)(((unsigned long long)hi << 32) | lo);
     };
     // lambda_i of the state after the step, plus the optional loss seed of
     // that state, s0 + c_i . s (affine in the velocity: the seeds of losses
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
         for (int c = 0; c <= D; ++c) sd[c] = seed[(long long)c * N + row0 + x];
     }
     auto lam_at = [&](int i) {
-        T v = *lane_ptr(lin + opaque((long long)i * N + row0), (unsigned)x);
+        T v = *lane_ptr(lin + uniform((long long)i * N + row0), (unsigned)x);
         if (seed) {
             v += sd[0];
 #pragma unroll
@@ -221,10 +223,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
         return v;
     };
     // adjoint of the pull: lam_n_i(x - c_i) = mu_i(x)
-    auto push = [&](int i, T m) {
-        const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
-        *lane_ptr(lout + opaque((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx), xs[cx]) = m;
-    };
+    auto push = [&](int i, T m) { *lane_ptr(lout + uniform((long long)i * N + pix.src_row(i)), pix.src_x(i)) = m; };
 
     // v: the stored values (g, or g - w when shifted), later x; l: lambda at
     // this cell, read here for <lambda, d> in the forward pass and again (a
@@ -233,9 +232,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
     T v[Q], l[Q];
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
-        const int cx = Lat<D>::c(i, 0) + 1, cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1;
-        const S *rowp = fn + ((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
-        v[i] = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
+        const S *rowp = fn + ((long long)i * N + pix.src_row(i));
+        v[i] = Storage<S>::to_T(*lane_ptr(rowp, pix.src_x(i)));
     }
 #pragma unroll
     for (int i = 0; i < Q; ++i) l[i] = lam_at(i);

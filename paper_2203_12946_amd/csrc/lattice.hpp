@@ -32,6 +32,54 @@ struct Lat {
 };
 
 // ---------------------------------------------------------------------------
+// Periodic pull addressing of one cell (Eq. advection): population i of cell
+// (x, y, z) is pulled from (x, y, z) - c_i mod (nx, ny, nz) and, in the
+// adjoint (and the in-place pull half), handed to the neighbour
+// (x, y, z) + c_i.  Along each axis the coordinate (coordinate - c) mod n of
+// a velocity component c is kept at index c + 1, so the neighbour + c sits
+// at index 1 - c.  A state or adjoint is Q fields [z][y][x] of N cells; a
+// row offset is the element offset of a row's first cell within one field,
+// a lane's x offset its position in the row.  The step, the in-place halves
+// and the adjoint take every element offset from here, and a host program in
+// the tests runs the same code over every cell of the tested and benchmarked
+// grids to check that each access is in bounds and that the pull (and the
+// adjoint's push) touches every element exactly once.
+// ---------------------------------------------------------------------------
+template <int D>
+struct PullIndex {
+    unsigned xs[3];
+    int ys[3], zs[3];
+    int nx, ny;
+    long long row0;  // the cell's own row
+    __host__ __device__ PullIndex(int x, int y, int z, int nx_, int ny_, int nz_) : nx(nx_), ny(ny_)
+    {
+        xs[0] = x + 1 == nx_ ? 0u : (unsigned)x + 1u;
+        xs[1] = (unsigned)x;
+        xs[2] = x == 0 ? (unsigned)nx_ - 1u : (unsigned)x - 1u;
+        ys[0] = y + 1 == ny_ ? 0 : y + 1;
+        ys[1] = y;
+        ys[2] = y == 0 ? ny_ - 1 : y - 1;
+        zs[0] = z + 1 == nz_ ? 0 : z + 1;
+        zs[1] = z;
+        zs[2] = z == 0 ? nz_ - 1 : z - 1;
+        row0 = ((long long)z * ny_ + y) * nx_;
+    }
+    // the row and x offset population i is pulled from: the cell - c_i
+    __host__ __device__ long long src_row(int i) const
+    {
+        return ((long long)zs[Lat<D>::c(i, 2) + 1] * ny + ys[Lat<D>::c(i, 1) + 1]) * nx;
+    }
+    __host__ __device__ unsigned src_x(int i) const { return xs[Lat<D>::c(i, 0) + 1]; }
+    // the row and x offset of the neighbour the cell's population i streams
+    // to: the cell + c_i
+    __host__ __device__ long long dst_row(int i) const
+    {
+        return ((long long)zs[1 - Lat<D>::c(i, 2)] * ny + ys[1 - Lat<D>::c(i, 1)]) * nx;
+    }
+    __host__ __device__ unsigned dst_x(int i) const { return xs[1 - Lat<D>::c(i, 0)]; }
+};
+
+// ---------------------------------------------------------------------------
 // Storage traits: T is the arithmetic type; load/store convert between the
 // stored value and the shifted deviation g - w.
 // ---------------------------------------------------------------------------

@@ -363,13 +363,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
 
     LaneStats ls;
     if (x < nx) {
-        // source coordinate of a population with velocity component c is
-        // (coordinate - c) mod n, indexed here by c + 1
-        const unsigned xs[3] = {x + 1 == nx ? 0u : (unsigned)x + 1u, (unsigned)x,
-                                x == 0 ? (unsigned)nx - 1u : (unsigned)x - 1u};
-        const int ys[3] = {y + 1 == ny ? 0 : y + 1, y, y == 0 ? ny - 1 : y - 1};
-        const int zs[3] = {z + 1 == nz ? 0 : z + 1, z, z == 0 ? nz - 1 : z - 1};
-        const long long row0 = ((long long)z * ny + y) * nx;
+        // source rows and x offsets of the pull (and, in place, the
+        // neighbours the pull half stores to)
+        const PullIndex<D> pix(x, y, z, nx, ny, nz);
+        const long long row0 = pix.row0;
         const long long cell = row0 + x;
 
         // p: the stored values as arithmetic type -- the populations g, or
@@ -383,9 +380,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
         auto pull = [&]() {
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
-                const int cy = Lat<D>::c(i, 1) + 1, cz = Lat<D>::c(i, 2) + 1, cx = Lat<D>::c(i, 0) + 1;
-                const S *rowp = fin + ((long long)i * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
-                p[i] = Storage<S>::to_T(*lane_ptr(rowp, xs[cx]));
+                const S *rowp = fin + ((long long)i * N + pix.src_row(i));
+                p[i] = Storage<S>::to_T(*lane_ptr(rowp, pix.src_x(i)));
             }
         };
         if constexpr (WALL) {
@@ -491,9 +487,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
             if constexpr (AA == kAAPull) {
                 // slot opp(i) of cell x + c_i, the location this lane read
                 // population opp(i) from
-                const int cx = 1 - Lat<D>::c(i, 0), cy = 1 - Lat<D>::c(i, 1), cz = 1 - Lat<D>::c(i, 2);
-                S *orow = fout + ((long long)(Q - 1 - i) * N + ((long long)zs[cz] * ny + ys[cy]) * nx);
-                Storage<S>::store_nt(lane_ptr(orow, xs[cx]), v);
+                S *orow = fout + ((long long)(Q - 1 - i) * N + pix.dst_row(i));
+                Storage<S>::store_nt(lane_ptr(orow, pix.dst_x(i)), v);
             } else {
                 S *orow = fout + ((long long)i * N + row0);
                 Storage<S>::store_nt(lane_ptr(orow, (unsigned)x), v);
