@@ -156,6 +156,45 @@ def test_adjoint_step_with_force(es):
     assert e1 < 1e-4 and e2 < 1e-4
 
 
+@pytest.mark.parametrize("D,shape", [
+    (3, (1, 1, 5)), (3, (1, 4, 1)), (3, (3, 1, 1)), (3, (2, 2, 129)), (3, (5, 1, 257)), (3, (2, 3, 300)),
+    (3, (2, 2, 513)), (2, (3, 257)), (2, (1, 300)), (2, (2, 1)),
+])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_adjoint_degenerate_and_ragged_grids(es, D, shape, dtype):
+    """The adjoint's push (lam_n_i(x - c_i) = mu_i(x)) and its reads of lambda
+    on grids of extent 1 or 2 along an axis (a population's neighbour is the
+    cell itself, or both neighbours are one cell), x rows one past a wave or
+    a block, and rows of several blocks (nx > 256, the last one ragged),
+    against the FP64 reference VJP; single precision with the body force."""
+    lat = "D2Q9" if D == 2 else "D3Q27"
+    f0 = three_regime_state(D, shape, 70 + shape[-1])
+    tau = 3e-3
+    lam = np.random.default_rng(shape[-1]).standard_normal(f0.shape)
+    F = W.random_force(shape, D, amplitude=1e-3, seed=5) if dtype == "f32" else None
+    ref, ref_F = _ref_vjp(f0, lam, tau, "higher", force=F)
+    s = es.Solver(lat, shape, dtype=dtype)
+    fg = None
+    if F is not None:
+        Fd = _t(F).float().cuda()
+        s.set_force(Fd)
+        fg = torch.zeros_like(Fd)
+    out = s.empty_adjoint()
+    out.fill_(float("nan"))  # an element the push missed stays NaN
+    s.adjoint_step(_t(f0).to(s.storage_dtype).cuda(), _t(lam).to(s.compute_dtype).cuda(), out, tau, force_grad=fg)
+    torch.cuda.synchronize()
+    got = out.double().cpu().numpy()
+    assert np.all(np.isfinite(got))
+    err = np.max(np.abs(got - ref)) / np.max(np.abs(ref))
+    msg = f"[vjp ragged {lat} {shape} {dtype}] max rel err = {err:.3e}"
+    if fg is not None:
+        eF = np.max(np.abs(fg.double().cpu().numpy() - ref_F)) / np.max(np.abs(ref_F))
+        msg += f", dF err = {eF:.3e}"
+        assert eF < 1e-4
+    _log(msg)
+    assert err < (1e-11 if dtype == "f64" else 1e-4)
+
+
 def test_kinetic_and_dissipation_seeds(es):
     shape = (6, 7, 9)
     f0 = _state(3, shape, 5, 1e-3)
