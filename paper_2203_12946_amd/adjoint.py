@@ -121,8 +121,10 @@ class _Equilibrium(torch.autograd.Function):
 class _Rollout(torch.autograd.Function):
     @staticmethod
     def forward(ctx, f0, force, solver, tau, nsteps, ckpt_every, diss_weight):
-        if force is not None:
-            solver.set_force(force.detach().contiguous())
+        # the rollout's force replaces whatever the solver had registered
+        # (None clears it), so the forward never runs with a stale force that
+        # the backward would not differentiate
+        solver.set_force(None if force is None else force.detach().contiguous())
         ro = Rollout(solver, tau, nsteps, ckpt_every, diss_weight)
         loss = torch.zeros(1, dtype=torch.float64, device=f0.device)
         fN = ro.forward(f0.detach().contiguous(), loss if diss_weight is not None else None)
@@ -167,7 +169,8 @@ def equilibrium(solver: Solver, rho: torch.Tensor, u: torch.Tensor) -> torch.Ten
 
 def rollout(solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
             force: torch.Tensor | None = None, diss_weight: float | None = None):
-    """(state after nsteps, accumulated dissipation loss)."""
+    """(state after nsteps, accumulated dissipation loss).  ``force`` becomes
+    the solver's registered body force for the rollout; None clears it."""
     return _Rollout.apply(f0, force, solver, tau, nsteps, ckpt_every, diss_weight)
 
 
