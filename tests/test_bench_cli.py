@@ -14,3 +14,11 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "--gpus 2" in r.stderr and "not implemented" in r.stderr
     assert r.stdout == ""
+
+
+def test_unknown_variant_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--variants", "f32_nonsense"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "unknown variants" in r.stderr
+    assert r.stdout == ""
