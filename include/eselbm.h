@@ -40,7 +40,10 @@
  * The library never frees caller memory.  It owns only the handle, a
  * small (under 10 KiB) device block of diagnostic accumulators and the wall
  * table, which eselbm_create allocates, and the losses' scratch (allocated
- * by the first loss call), all of which eselbm_destroy frees.
+ * by the first loss call), all of which eselbm_destroy frees.  Besides, each
+ * device the library runs on holds one fixed 512 KiB array of partial sums
+ * for eselbm_kinetic_loss_noalloc until the process ends (it is part of the
+ * loaded code, not allocated by any call).
  *
  * Streams: `stream` is a hipStream_t passed as void*; NULL is the default
  * stream.  All kernels are enqueued on it asynchronously.  Only
@@ -282,6 +285,21 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
  * output may be NULL.  Scratch: as for eselbm_dissipation_loss. */
 eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,
                                   double scale, void *stream);
+
+/* The kinetic-energy loss of eselbm_kinetic_loss for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It calls no allocating routine: its
+ * partial sums (one double per 256 cells) live in a fixed device array of
+ * 2^16 doubles (512 KiB) that the library holds on each device for the life
+ * of the process, so it serves grids of at most 2^24 cells
+ * (ESELBM_E_UNSUPPORTED beyond).  Same arguments, kernels and summation
+ * order as eselbm_kinetic_loss, hence the same results to the bit.  Every
+ * call on a device shares that array: calls that overlap on one device (on
+ * different streams or from different threads) race and must be
+ * serialised by the caller.  Each call writes every partial sum it reads, so
+ * nothing carries over from the previous call. */
+eselbm_status eselbm_kinetic_loss_noalloc(eselbm_handle h, const void *f, double *loss_dev, void *lam,
+                                          double scale, void *stream);
 
 /* Dissipation loss term of one state and its seed (not in the paper):
  * L = weight * sum_x |omega(x)|^2 with omega the vorticity from periodic

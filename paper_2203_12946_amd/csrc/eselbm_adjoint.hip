@@ -18,6 +18,7 @@
 #include "internal.hpp"
 #include "lattice.hpp"
 
+#include <mutex>
 #include <type_traits>
 
 namespace eselbm {
@@ -753,16 +754,16 @@ static hipError_t ensure_scratch(LossScratch &sc, const Grid &g)
     return hipSuccess;
 }
 
+// The kinetic loss's kernels with an explicit buffer of one partial sum per
+// 256-cell block (every entry the sum reads is written first).
 template <int D>
-static hipError_t launch_kin_d(LossScratch &sc, int dtype, const Grid &g, const void *f, double *loss, void *lam,
-                               double scale, hipStream_t s)
+static hipError_t launch_kin_parts(double *parts, int dtype, const Grid &g, const void *f, double *loss, void *lam,
+                                   double scale, hipStream_t s)
 {
-    hipError_t e = ensure_scratch(sc, g);
-    if (e != hipSuccess) return e;
     const long long nblk = (g.N + 255) / 256;
     if (nblk > 0x7fffffffLL) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)nblk), block(256);
-    double *part = loss ? sc.part : nullptr;
+    double *part = loss ? parts : nullptr;
     if (dtype == 0)
         hipLaunchKernelGGL((k_kinetic<D, double>), grid, block, 0, s, g, (const double *)f, part, (double *)lam, scale);
     else if (dtype == 1)
@@ -778,8 +779,47 @@ static hipError_t launch_kin_d(LossScratch &sc, int dtype, const Grid &g, const 
 hipError_t launch_kinetic_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, double *loss, void *lam,
                                double scale, hipStream_t s)
 {
-    return g.D == 2 ? launch_kin_d<2>(sc, dtype, g, f, loss, lam, scale, s)
-                    : launch_kin_d<3>(sc, dtype, g, f, loss, lam, scale, s);
+    hipError_t e = ensure_scratch(sc, g);
+    if (e != hipSuccess) return e;
+    return g.D == 2 ? launch_kin_parts<2>(sc.part, dtype, g, f, loss, lam, scale, s)
+                    : launch_kin_parts<3>(sc.part, dtype, g, f, loss, lam, scale, s);
+}
+
+// ---------------------------------------------------------------------------
+// The kinetic loss without allocation (eselbm_kinetic_loss_noalloc): its
+// partial sums live in a file-scope device array of kNoAllocParts doubles
+// (512 KiB: grids of up to 2^24 cells), which each device holds for the
+// life of the process.  Host code never passes the array's name to a kernel
+// (on the host it stands in for the symbol, not a device address): the
+// device address is looked up once per device with that device current and
+// kept in a per-device table.
+// ---------------------------------------------------------------------------
+static __device__ __align__(256) double scratch[kNoAllocParts];
+
+static std::mutex g_scratch_mu;
+static double *g_scratch_ptr[kMaxDevices];
+
+hipError_t noalloc_scratch(int device, double **out)
+{
+    *out = nullptr;
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        double *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[device] = ptr;
+    }
+    *out = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_kinetic_loss_noalloc(double *parts, int dtype, const Grid &g, const void *f, double *loss,
+                                       void *lam, double scale, hipStream_t s)
+{
+    if ((g.N + 255) / 256 > kNoAllocParts) return hipErrorInvalidValue;
+    return g.D == 2 ? launch_kin_parts<2>(parts, dtype, g, f, loss, lam, scale, s)
+                    : launch_kin_parts<3>(parts, dtype, g, f, loss, lam, scale, s);
 }
 
 // ---------------------------------------------------------------------------

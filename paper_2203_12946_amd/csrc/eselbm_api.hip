@@ -29,6 +29,7 @@ struct eselbm_ctx {
     double *wall_eq;       // device [2 D][Q], inside the dev_stats allocation
     double prandtl;        // ES-BGK Prandtl number; 1: the equilibrium itself
     LossScratch loss_scratch;  // the losses' buffers on this handle's device, grown on demand
+    double *noalloc_parts;     // the device's fixed partial-sum array (eselbm_kinetic_loss_noalloc)
 };
 
 static thread_local std::string g_err;
@@ -100,6 +101,14 @@ eselbm_status eselbm_create(eselbm_handle *out, int lattice, int nx, int ny, int
         return hip_fail(e, "eselbm_create: hipMalloc");
     }
     h->wall_eq = (double *)(h->dev_stats + kStatSlots);
+    // the device address of the allocation-free kinetic loss's fixed array,
+    // looked up once per device (this device is current here)
+    e = noalloc_scratch(h->device, &h->noalloc_parts);
+    if (e != hipSuccess) {
+        hipFree(h->dev_stats);
+        delete h;
+        return hip_fail(e, "eselbm_create: device address of the fixed loss buffer");
+    }
     *out = h;
     return ESELBM_OK;
 }
@@ -382,6 +391,22 @@ eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_d
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_kinetic_loss: F16 storage");
     hipError_t e = launch_kinetic_loss(h->loss_scratch, h->dtype, h->g, f, loss_dev, lam, scale, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_kinetic_loss: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_kinetic_loss_noalloc(eselbm_handle h, const void *f, double *loss_dev, void *lam, double scale,
+                                          void *stream)
+{
+    if (!h || !f) return fail(ESELBM_E_ARG, "eselbm_kinetic_loss_noalloc: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_kinetic_loss_noalloc")) return st;
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_kinetic_loss_noalloc: F16 storage");
+    if ((h->g.N + 255) / 256 > kNoAllocParts)
+        return fail(ESELBM_E_UNSUPPORTED,
+                    "eselbm_kinetic_loss_noalloc: grids of more than 2^24 cells exceed its fixed partial-sum buffer");
+    if (!h->noalloc_parts) return fail(ESELBM_E_HIP, "eselbm_kinetic_loss_noalloc: no fixed buffer on this device");
+    hipError_t e = launch_kinetic_loss_noalloc(h->noalloc_parts, h->dtype, h->g, f, loss_dev, lam, scale,
+                                               (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_kinetic_loss_noalloc: launch");
     return ESELBM_OK;
 }
 

@@ -78,6 +78,15 @@ struct LossScratch {
 hipError_t free_loss_scratch(LossScratch &sc);
 hipError_t launch_kinetic_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, double *loss, void *lam,
                                double scale, hipStream_t s);
+// The kinetic loss for callers that cannot allocate: its partial sums in a
+// file-scope device array of kNoAllocParts doubles per device (grids of up to
+// 256 * kNoAllocParts cells).  noalloc_scratch looks up that array's device
+// address on `device`, which must be current, once, and returns it after.
+constexpr long long kNoAllocParts = 1 << 16;
+constexpr int kMaxDevices = 256;
+hipError_t noalloc_scratch(int device, double **out);
+hipError_t launch_kinetic_loss_noalloc(double *parts, int dtype, const Grid &g, const void *f, double *loss,
+                                       void *lam, double scale, hipStream_t s);
 hipError_t launch_dissipation_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *force,
                                    double *loss, void *lam, void *seed, double weight, float *force_grad,
                                    hipStream_t s);

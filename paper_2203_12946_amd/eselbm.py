@@ -69,6 +69,7 @@ _SIGNATURES = {
     "eselbm_moments": [_vp, _vp, _vp, _vp, _vp],
     "eselbm_adjoint_step": [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_kinetic_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
+    "eselbm_kinetic_loss_noalloc": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
     "eselbm_dissipation_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_dissipation_seed": [_vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_equilibrium_vjp": [_vp, _vp, _vp, _vp, _vp, _vp],
@@ -279,6 +280,16 @@ class Solver:
     def kinetic_loss(self, f, loss=None, lam=None, scale: float = 1.0, stream=None):
         with self._on():
             _check(lib.eselbm_kinetic_loss(
+                self._h, self._p(f, self.storage_dtype, self.Q * self.cells),
+                self._p(loss, torch.float64, 1) if loss is not None else _vp(None),
+                self._p(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
+                float(scale), _stream(stream)))
+
+    def kinetic_loss_noalloc(self, f, loss=None, lam=None, scale: float = 1.0, stream=None):
+        """kinetic_loss without any allocation (a fixed per-device buffer;
+        grids of at most 2^24 cells; overlapping calls on one device race)."""
+        with self._on():
+            _check(lib.eselbm_kinetic_loss_noalloc(
                 self._h, self._p(f, self.storage_dtype, self.Q * self.cells),
                 self._p(loss, torch.float64, 1) if loss is not None else _vp(None),
                 self._p(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
