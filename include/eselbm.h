@@ -182,6 +182,17 @@ eselbm_status eselbm_set_alpha_field(eselbm_handle h, void *alpha);
  * it.  Cells that were not collided receive NaN. */
 eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut);
 
+/* Registers a device float buffer uv of [D + 1][cells] values that
+ * receives, for the output state of the last step of each eselbm_step call,
+ * the velocity u_a = (sum_i c_ia f_i + F_a / 2) / rho (the half-force shift
+ * with a body force registered, as eselbm_moments reports it) in uv[a] and
+ * the density rho in uv[D], in single precision.  The step forms them from
+ * the moments it already holds, so a loss that depends on the state only
+ * through u and rho (eselbm_dissipation_loss_uv) needs no pass over the
+ * state (not in the paper).  NULL disables it.  Walled, ES-BGK and the
+ * mirror-condition steps fill it too. */
+eselbm_status eselbm_set_velocity_field(eselbm_handle h, float *uv);
+
 /* Bounds the grid by walls (not part of the method; the lid-driven cavity of
  * Sec. V C uses them).  walls: bit a set (a = 0 x, 1 y, 2 z) bounds axis a by
  * walls half-way outside its first and last nodes; 0 restores a fully
@@ -326,6 +337,18 @@ eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *lo
  * eselbm_dissipation_loss.  Scratch: as for eselbm_dissipation_loss. */
 eselbm_status eselbm_dissipation_seed(eselbm_handle h, const void *f, void *seed, double weight,
                                       void *force_grad, void *stream);
+
+/* The dissipation loss of eselbm_dissipation_loss, and its seed, from the
+ * velocity and density field of a state (uv: device float [D + 1][cells] as
+ * eselbm_set_velocity_field receives it) instead of the state itself (not in
+ * the paper).  The value is ADDED to *loss_dev.  lam (the full seed, ADDED,
+ * compute type [Q][cells]) or seed (the compact seed (s0, s), overwritten,
+ * compute type [1 + D][cells]) receives the seed; at most one of them
+ * (ESELBM_E_ARG otherwise).  With a force registered, the direct part of
+ * dL/dF is ADDED to force_grad.  Any output may be NULL.  Scratch: as for
+ * eselbm_dissipation_loss. */
+eselbm_status eselbm_dissipation_loss_uv(eselbm_handle h, const float *uv, double *loss_dev, void *lam, void *seed,
+                                         double weight, void *force_grad, void *stream);
 
 /* Adjoint of eselbm_init_equilibrium with respect to u (rho held fixed):
  * grad_u[a][x] = sum_i lam[i][x] d feq_i(rho, u)/d u_a.

@@ -5,13 +5,15 @@ schedules them:
 
 * ``Rollout.forward`` runs n steps, keeping the state every ``ckpt_every``
   steps (checkpoints) and, optionally, accumulating a dissipation loss
-  weight * sum_x |omega|^2 after every step.
+  weight * sum_x |omega|^2 after every step.  The step itself writes the
+  velocity and density of its output (the loss depends on the state only
+  through them), so the loss reads that field instead of the state.
 * ``Rollout.backward`` sweeps the checkpoint segments in reverse.  For each
-  segment it recomputes the segment's states from its checkpoint, then applies
-  the adjoint step kernel from the last state down to the first.  The
-  per-step loss seeds travel in compact per-cell form (dL/df_i = s0 + c_i.s)
-  and each is added by the adjoint step that reads it.  The adjoint kernel
-  also accumulates the body-force gradient.
+  segment it recomputes the segment's states from its checkpoint (with their
+  velocity fields), then applies the adjoint step kernel from the last state
+  down to the first.  The per-step loss seeds travel in compact per-cell form
+  (dL/df_i = s0 + c_i.s) and each is added by the adjoint step that reads it.
+  The adjoint kernel also accumulates the body-force gradient.
 
 Autograd functions wrap the three pieces of a training objective:
 ``equilibrium`` (initial state from rho, u; gradient w.r.t. u), ``rollout``
@@ -36,6 +38,16 @@ class Rollout:
         self.K = int(ckpt_every)
         self.diss_weight = diss_weight
         self.ckpts: dict[int, torch.Tensor] = {}
+        self.uv_end: torch.Tensor | None = None
+
+    def _step_with_velocity(self, f: torch.Tensor, out: torch.Tensor, uv: torch.Tensor):
+        """One step f -> out that also writes out's velocity field into uv."""
+        s = self.s
+        s.set_velocity_field(uv)
+        try:
+            s.step(f, out, 1, self.tau)
+        finally:
+            s.set_velocity_field(None)
 
     def forward(self, f0: torch.Tensor, loss_acc: torch.Tensor | None = None) -> torch.Tensor:
         """State after nsteps; with a dissipation weight, adds the loss of
@@ -44,13 +56,21 @@ class Rollout:
         cur = f0.clone()
         nxt = s.empty_state()
         self.ckpts = {0: cur.clone()}
+        with_loss = self.diss_weight is not None and loss_acc is not None
+        uv = s.empty_velocity() if with_loss else None
+        self.uv_end = None
         for n in range(self.nsteps):
-            s.step(cur, nxt, 1, self.tau)
+            if with_loss:
+                self._step_with_velocity(cur, nxt, uv)
+            else:
+                s.step(cur, nxt, 1, self.tau)
             cur, nxt = nxt, cur
-            if self.diss_weight is not None and loss_acc is not None:
-                s.dissipation_loss(cur, loss=loss_acc, weight=self.diss_weight)
+            if with_loss:
+                s.dissipation_loss_uv(uv, loss=loss_acc, weight=self.diss_weight)
             if (n + 1) % self.K == 0 and (n + 1) < self.nsteps:
                 self.ckpts[n + 1] = cur.clone()
+        if with_loss:
+            self.uv_end = uv
         return cur
 
     def backward(self, lam_final: torch.Tensor | None, diss_grad: float = 0.0,
@@ -71,16 +91,25 @@ class Rollout:
         pending = None
         n_end = self.nsteps
         if w:
-            s.dissipation_seed(self._state_at_end(), seed, weight=w, force_grad=force_grad)
+            if self.uv_end is not None:
+                s.dissipation_loss_uv(self.uv_end, seed=seed, weight=w, force_grad=force_grad)
+            else:
+                s.dissipation_seed(self._state_at_end(), seed, weight=w, force_grad=force_grad)
             pending = seed
         seg_starts = sorted(self.ckpts)
         for start in reversed(seg_starts):
             stop = min(start + self.K, n_end)
-            # states f^start .. f^(stop-1)
+            # states f^start .. f^(stop-1); with the loss, the velocity field
+            # of each recomputed one (the checkpoint's seed reads the state)
             states = [self.ckpts[start]]
+            uvs = [None]
             for _ in range(start, stop - 1):
                 nxt = s.empty_state()
-                s.step(states[-1], nxt, 1, self.tau)
+                if w:
+                    uvs.append(s.empty_velocity())
+                    self._step_with_velocity(states[-1], nxt, uvs[-1])
+                else:
+                    s.step(states[-1], nxt, 1, self.tau)
                 states.append(nxt)
             for n in range(stop - 1, start - 1, -1):
                 f_n = states[n - start]
@@ -88,7 +117,10 @@ class Rollout:
                 lam, other = other, lam
                 pending = None
                 if w and n >= 1:
-                    s.dissipation_seed(f_n, seed, weight=w, force_grad=force_grad)
+                    if uvs[n - start] is not None:
+                        s.dissipation_loss_uv(uvs[n - start], seed=seed, weight=w, force_grad=force_grad)
+                    else:
+                        s.dissipation_seed(f_n, seed, weight=w, force_grad=force_grad)
                     pending = seed
             n_end = start
         return lam

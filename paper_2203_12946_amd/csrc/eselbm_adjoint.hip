@@ -142,13 +142,15 @@ __device__ inline void root_bar(T s, T A, T B, T sbar, T &Ab, T &Bb, T &Cb)
 
 // Occupancy floor of the adjoint step.  The adjoint is ALU-bound (about
 // twice its memory time); the Q values of x and of lambda, the equilibrium
-// tables and the adjoints of the sums need about 190 VGPRs in single
+// tables and the adjoints of the sums need 170-190 VGPRs in single
 // precision, so two waves per SIMD run without scratch.  At three waves
-// (168 VGPRs) the spilled version measured the same time at 128^3.
-template <typename S>
-struct AdjPolicy {
-    static constexpr int waves = 2;
-};
+// (168 VGPRs) the forced alpha_Higher adjoint fits with 8 bytes of scratch
+// but measured 294 us against 207 us at two (128^3).
+template <typename S, int MODE>
+constexpr int adj_waves()
+{
+    return 2;
+}
 
 // Adjoint (vector-Jacobian product) of one step at one cell.
 //
@@ -170,7 +172,7 @@ struct AdjPolicy {
 // Gated cells carry no alpha derivative; a guarded cell's alpha depends on
 // x_min alone; the Omega+- membership is that of the point.
 template <int D, typename S, int MODE, bool FORCE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S>::waves))) void k_adjoint(AdjArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S, MODE>()))) void k_adjoint(AdjArgs a)
 {
     using T = typename Storage<S>::T;
     constexpr int Q = Lat<D>::Q;
@@ -275,8 +277,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
         }
 
         // ---- forward: x, lambda . d, x_min, max|x| and the power moments
-        T lamd = T(0), xmin = T(0), gxm = T(1), xabs = T(0);
-        int imin = -1;
+        T lamd = T(0), xmin = T(0), xabs = T(0);
         T Tm[K + 1], Nm[K + 1];
 #pragma unroll
         for (int k = 0; k <= K; ++k) Tm[k] = Nm[k] = T(0);
@@ -290,11 +291,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
                 T xi = d * rcp_(g);
                 // x as one value from here on (not d and 1/g kept apart)
                 asm volatile("" : "+v"(xi));
-                if (xi < xmin) {
-                    xmin = xi;
-                    gxm = g;
-                    imin = i;
-                }
+                xmin = fmin_(xmin, xi);
                 xabs = fmax_(xabs, abs_(xi));
                 T xk[K];
                 xk[1] = xi;
@@ -315,7 +312,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
         for (int k = 2; k <= K; ++k) asm volatile("" : "+v"(Tm[k]));
 #pragma unroll
         for (int k = 3; k <= K; ++k) asm volatile("" : "+v"(Nm[k]));
-        asm volatile("" : "+v"(lamd), "+v"(xmin), "+v"(xabs), "+v"(gxm));
+        asm volatile("" : "+v"(lamd), "+v"(xmin), "+v"(xabs));
 
         // ---- forward path length, and the adjoints of the sums it used ----
         const bool gated = MODE == MODE_BGK || xabs < T(kGate);
@@ -480,6 +477,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
             }
         }
         const bool smooth = !gated && !guarded;
+        // A guarded cell's alpha depends on its smallest x_i alone: the first
+        // population with x_i = x_min (the lowest index on ties), whose g is
+        // feq / (1 + x).  Found here, and only in waves that hold a guarded
+        // cell (any_guard is wave-uniform), so that the common path carries
+        // no argmin.
+        const bool any_guard = __ballot(guarded) != 0ull;
+        int imin = -1;
+        T xdmin = T(0);
+        if (any_guard && guarded) {
+            const Equilibrium<D, T> eq(drho, u);
+            T gxm = T(1);
+#pragma unroll
+            for (int i = 0; i < Q; ++i) {
+                if (imin < 0 && v[i] == xmin) {
+                    imin = i;
+                    gxm = (T(Lat<D>::w(i)) + eq.dev(i)) * rcp_(T(1) + v[i]);
+                }
+            }
+            xdmin = xminb * rcp_(gxm);
+        }
         const T ab = alpha * beta;
         const T lfac = FORCE ? ab - T(1) : ab;
         // feq enters out with weight alpha beta (alpha beta - 1 with forcing,
@@ -511,7 +528,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
         // the form they were validated in).
         T F[3][3], dF[3][3];
         axis_factors_d<D, T>(u, F, dF);
-        const T xdmin = guarded ? xminb * rcp_(gxm) : T(0);
         // x enters each pass as a fresh copy (empty asm), so that the powers
         // of x formed in one pass are not kept live for the next
         auto xcopy = [&](int i) {
@@ -519,14 +535,17 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
             asm volatile("" : "+v"(xi));
             return xi;
         };
-        auto passes = [&](auto &&dirxd) {
+        // GUARD: the wave holds a guarded cell, whose x_min population takes
+        // xd = xdmin
+        auto passes = [&](auto &&dirxd, auto guard) {
             constexpr bool keep_mu = !std::is_same<T, double>::value;
+            constexpr bool GUARD = decltype(guard)::value;
 #pragma unroll
             for (int i = 0; i < Q; ++i) {
                 T dir, xd;
                 const T xi = xcopy(i);
                 dirxd(xi, dir, xd);
-                if (guarded && i == imin) xd = xdmin;
+                if (GUARD && i == imin) xd = xdmin;
                 T gp[3];
                 const T Pi = prod_and_grad<D, T>(i, F, dF, gp);
                 rhob = fma_(xd, Pi, rhob);
@@ -558,7 +577,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
                     T dir, xd;
                     const T xi = xcopy(i);
                     dirxd(xi, dir, xd);
-                    if (guarded && i == imin) xd = xdmin;
+                    if (GUARD && i == imin) xd = xdmin;
                     m = fma_(l[i], T(1) - ab, dir) - (T(1) + xi) * xd + rhob;
                 }
 #pragma unroll
@@ -580,7 +599,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
                 cP[k] = smooth ? Tb[k] : T(0);
                 cN[k] = smooth ? Tb[k] + Nb[k] : T(0);
             }
-            passes([&](T xi, T &dir, T &xd) {
+            auto series = [&](T xi, T &dir, T &xd) {
                 const bool neg = xi < T(0);
                 T pv = neg ? cN[K] : cP[K], pd = T(K) * pv;
 #pragma unroll
@@ -591,7 +610,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
                 }
                 dir = pv * xi * xi;
                 xd = pd * xi;
-            });
+            };
+            if (any_guard) passes(series, std::true_type{});
+            else passes(series, std::false_type{});
         } else {
             // exact rationals
             passes([&](T xi, T &dir, T &xd) {
@@ -622,7 +643,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(AdjPolicy<S
                     dir += Bpb * x3 * R;
                     xd += Bpb * (T(3) * x2 * R + x3 * aLx * dR);
                 }
-            });
+            }, std::false_type{});
         }
     } else {
         // uncollided cell: out = g, so mu = lambda
@@ -974,48 +995,55 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restri
 }
 
 template <int D>
-static hipError_t launch_diss_d(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *force,
-                                double *loss, void *lam, void *seed, double weight, float *force_grad, hipStream_t s)
+static hipError_t launch_diss_d(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *uv,
+                                const float *force, double *loss, void *lam, void *seed, double weight,
+                                float *force_grad, hipStream_t s)
 {
     hipError_t e = ensure_scratch(sc, g);
     if (e != hipSuccess) return e;
     const long long nflat = (g.N + 255) / 256;
     if (nflat > 0x7fffffffLL || g.ny > 65535 || g.nz > 65535) return hipErrorInvalidConfiguration;
     const dim3 grid((unsigned)nflat), block(256);
-    if (dtype == 0)
+    // velocity and density: a pass over the state, or the field a step wrote
+    const float *u = sc.u, *rho = sc.rho;
+    if (!f) {
+        u = uv;
+        rho = uv + (long long)D * g.N;
+    } else if (dtype == 0) {
         hipLaunchKernelGGL((k_velocity<D, double>), grid, block, 0, s, g, (const double *)f, force, sc.u,
                            sc.rho);
-    else if (dtype == 1)
+    } else if (dtype == 1) {
         hipLaunchKernelGGL((k_velocity<D, float>), grid, block, 0, s, g, (const float *)f, force, sc.u,
                            sc.rho);
-    else if (dtype == 3)
+    } else if (dtype == 3) {
         hipLaunchKernelGGL((k_velocity<D, f32s>), grid, block, 0, s, g, (const f32s *)f, force, sc.u,
                            sc.rho);
-    else
+    } else {
         return hipErrorInvalidValue;
+    }
     const int bx = block_x(g.nx);
     const dim3 sgrid((unsigned)((g.nx + bx - 1) / bx), (unsigned)g.ny, (unsigned)g.nz), sblock(bx);
     double *part = loss ? sc.part : nullptr;
-    hipLaunchKernelGGL((k_vorticity<D>), sgrid, sblock, 0, s, g, sc.u, sc.vort, part, weight);
+    hipLaunchKernelGGL((k_vorticity<D>), sgrid, sblock, 0, s, g, u, sc.vort, part, weight);
     if (loss)
         hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (const double *)part, stencil_blocks(g), loss);
     if (lam || seed || force_grad) {
         if (dtype == 0)
-            hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, sc.u, sc.rho,
+            hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, u, rho,
                                sc.vort, (double *)lam, (double *)seed, weight, force_grad);
         else
-            hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, sc.u, sc.rho,
+            hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, u, rho,
                                sc.vort, (float *)lam, (float *)seed, weight, force_grad);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_dissipation_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *force,
-                                   double *loss, void *lam, void *seed, double weight, float *force_grad,
-                                   hipStream_t s)
+hipError_t launch_dissipation_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *uv,
+                                   const float *force, double *loss, void *lam, void *seed, double weight,
+                                   float *force_grad, hipStream_t s)
 {
-    return g.D == 2 ? launch_diss_d<2>(sc, dtype, g, f, force, loss, lam, seed, weight, force_grad, s)
-                    : launch_diss_d<3>(sc, dtype, g, f, force, loss, lam, seed, weight, force_grad, s);
+    return g.D == 2 ? launch_diss_d<2>(sc, dtype, g, f, uv, force, loss, lam, seed, weight, force_grad, s)
+                    : launch_diss_d<3>(sc, dtype, g, f, uv, force, loss, lam, seed, weight, force_grad, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -22,6 +22,7 @@ struct eselbm_ctx {
     int device;
     void *alpha_field;
     void *nut_field;
+    float *uv_field;       // velocity and density of the last step's output, or null
     const float *force;
     const void *last_out;  // output state of the last statistics-enabled step
     DevStats *dev_stats;   // kStatSlots slots, then the wall table
@@ -160,6 +161,13 @@ eselbm_status eselbm_set_nut_field(eselbm_handle h, void *nut)
     return ESELBM_OK;
 }
 
+eselbm_status eselbm_set_velocity_field(eselbm_handle h, float *uv)
+{
+    if (!h) return fail(ESELBM_E_ARG, "eselbm_set_velocity_field: NULL handle");
+    h->uv_field = uv;
+    return ESELBM_OK;
+}
+
 eselbm_status eselbm_set_prandtl(eselbm_handle h, double prandtl)
 {
     if (!h) return fail(ESELBM_E_ARG, "eselbm_set_prandtl: NULL handle");
@@ -273,10 +281,14 @@ eselbm_status eselbm_step(eselbm_handle h, void *f_in, void *f_out, int nsteps, 
         sa.wall_eq = h->wall_eq;
         sa.alpha_out = last ? h->alpha_field : nullptr;
         sa.nut_out = last ? h->nut_field : nullptr;
+        sa.uv_out = last ? h->uv_field : nullptr;
         sa.stats = (last && h->stats_on) ? h->dev_stats : nullptr;
         sa.cpr = cpr;
         sa.aa = in_place ? (k % 2 == 0 ? 1 : 2) : 0;
-        const bool diag = sa.alpha_out != nullptr || sa.nut_out != nullptr || sa.stats != nullptr;
+        // the forced step writes the velocity field itself; the others do it
+        // in their diagnostic variant
+        const bool diag = sa.alpha_out != nullptr || sa.nut_out != nullptr || sa.stats != nullptr ||
+                          (sa.uv_out != nullptr && !sa.force);
         if (sa.stats) {
             hipError_t e = launch_reset_stats(h->dev_stats, s);
             if (e != hipSuccess) return hip_fail(e, "eselbm_step: reset");
@@ -418,8 +430,8 @@ eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *lo
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss: force_grad without a registered force");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss: periodic differences only");
-    hipError_t e = launch_dissipation_loss(h->loss_scratch, h->dtype, h->g, f, h->force, loss_dev, lam, nullptr, weight,
-                                           (float *)force_grad, (hipStream_t)stream);
+    hipError_t e = launch_dissipation_loss(h->loss_scratch, h->dtype, h->g, f, nullptr, h->force, loss_dev, lam, nullptr,
+                                           weight, (float *)force_grad, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_loss: launch");
     return ESELBM_OK;
 }
@@ -432,9 +444,24 @@ eselbm_status eselbm_dissipation_seed(eselbm_handle h, const void *f, void *seed
     if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: F16 storage");
     if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_seed: force_grad without a registered force");
     if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_seed: periodic differences only");
-    hipError_t e = launch_dissipation_loss(h->loss_scratch, h->dtype, h->g, f, h->force, nullptr, nullptr, seed, weight,
-                                           (float *)force_grad, (hipStream_t)stream);
+    hipError_t e = launch_dissipation_loss(h->loss_scratch, h->dtype, h->g, f, nullptr, h->force, nullptr, nullptr, seed,
+                                           weight, (float *)force_grad, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_seed: launch");
+    return ESELBM_OK;
+}
+
+eselbm_status eselbm_dissipation_loss_uv(eselbm_handle h, const float *uv, double *loss_dev, void *lam, void *seed,
+                                         double weight, void *force_grad, void *stream)
+{
+    if (!h || !uv) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss_uv: NULL argument");
+    if (eselbm_status st = device_check(h, "eselbm_dissipation_loss_uv")) return st;
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss_uv: F16 storage");
+    if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss_uv: force_grad without a registered force");
+    if (lam && seed) return fail(ESELBM_E_ARG, "eselbm_dissipation_loss_uv: give lam or seed, not both");
+    if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_dissipation_loss_uv: periodic differences only");
+    hipError_t e = launch_dissipation_loss(h->loss_scratch, h->dtype, h->g, nullptr, uv, h->force, loss_dev, lam, seed,
+                                           weight, (float *)force_grad, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "eselbm_dissipation_loss_uv: launch");
     return ESELBM_OK;
 }
 

@@ -35,6 +35,7 @@ struct StepArgs {
     const double *wall_eq;   // [2 D][Q]: feq_i(1, u_wall) - w_i of wall 2 a + side
     void *alpha_out;     // [N] compute type or null
     void *nut_out;       // [N] compute type or null: nu_T of Eq. nuT
+    float *uv_out;       // [D + 1][N] or null: u (with the half-force shift) and rho of the output state
     DevStats *stats;     // kStatSlots slots or null
     double cpr;          // ES-BGK stress factor c_Pr; 0: the equilibrium itself
     int aa;              // 0: two lattices (fin -> fout); in place: 1 the pull half, 2 the local half
@@ -87,9 +88,12 @@ constexpr int kMaxDevices = 256;
 hipError_t noalloc_scratch(int device, double **out);
 hipError_t launch_kinetic_loss_noalloc(double *parts, int dtype, const Grid &g, const void *f, double *loss,
                                        void *lam, double scale, hipStream_t s);
-hipError_t launch_dissipation_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *force,
-                                   double *loss, void *lam, void *seed, double weight, float *force_grad,
-                                   hipStream_t s);
+// The dissipation loss from a state f (its velocity and density formed by a
+// pass over f), or, with f null, from uv, the [D + 1][N] velocity and
+// density field a step wrote (eselbm_set_velocity_field).
+hipError_t launch_dissipation_loss(LossScratch &sc, int dtype, const Grid &g, const void *f, const float *uv,
+                                   const float *force, double *loss, void *lam, void *seed, double weight,
+                                   float *force_grad, hipStream_t s);
 hipError_t launch_equilibrium_vjp(int dtype, const Grid &g, const double *rho, const double *u,
                                   const void *lam, double *grad_u, hipStream_t s);
 

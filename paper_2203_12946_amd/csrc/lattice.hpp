@@ -414,7 +414,10 @@ constexpr double kGate = 1e-3;
 // all have |x| < X; the truncation after x^K (y^(K-3) for R) is below the
 // rounding of the arithmetic type there:
 //   float,  X = 0.02,  K = 6: c1, c, b within 1e-10, 6e-10, 5e-9 relative;
-//   double, X = 0.005, K = 8: c1, c within 1e-18, 2e-17 and b within 1e-17.
+//   double, X = 0.005, K = 7: c1, c within 3e-16, 2e-15 and b within 2e-14
+//           relative, alpha within 3e-15: its error moves the update by
+//           below 2e-17 of g per step (x <= 0.005), under the storage's
+//           rounding.
 template <typename T>
 struct SeriesCfg;
 template <>
@@ -424,8 +427,17 @@ struct SeriesCfg<float> {
 };
 template <>
 struct SeriesCfg<double> {
-    static constexpr int K = 8;
+    static constexpr int K = 7;
     static constexpr double X = 0.005;
+};
+// FP16-shifted storage: its rounding (2^-11 of a deviation g - w) moves
+// alpha by about 1e-4 from one step to the next, so the sums need far less
+// than float precision.  K = 4 at X = 0.01: c1 and c within 1.3e-7 and
+// 2.5e-7, b within 1e-6 relative, and the N5, N6 terms of a (not formed)
+// below 1.2e-4 of a, which moves alpha by under 2e-6 relative.
+struct SeriesCfgF16 {
+    static constexpr int K = 4;
+    static constexpr double X = 0.01;
 };
 
 template <typename T>
@@ -453,20 +465,35 @@ __device__ inline T higher_from_coeffs(T aL, T b1, T Bp, T C, T N3, T N4, T N5, 
 }
 
 // Population i from the stored value p_i: p is g itself, or the deviation
-// g - w when SH (shifted storage).
-template <int D, typename T, bool SH>
-__device__ inline T gval(int i, const T (&p)[Lat<D>::Q])
+// g - w when SH (shifted storage).  p is an array of the Q stored values or
+// a PopAccess (below).
+template <int D, typename T, bool SH, typename P>
+__device__ inline T gval(int i, const P &p)
 {
-    return SH ? T(Lat<D>::w(i)) + p[i] : p[i];
+    return SH ? T(Lat<D>::w(i)) + T(p[i]) : T(p[i]);
 }
+
+// The stored values of a cell's pulled populations, the first NS of them in
+// the lane's column of an LDS array [NS][kStashStride] (each lane reads back
+// only what it wrote), the other Q - NS in registers; NS = 0 keeps them all
+// in registers.  A step whose registers cannot hold the Q values beside d and
+// the path-length sums at the occupancy it needs parks them there once the
+// moments are formed.
+constexpr int kStashStride = 256;  // the largest block
+template <typename T, int Q, int NS>
+struct PopAccess {
+    const T *col;  // &lds[threadIdx.x] when NS > 0
+    T tail[Q - NS];
+    __device__ T operator[](int i) const { return i < NS ? col[i * kStashStride] : tail[i - NS]; }
+};
 
 // Exact rational sums in the arithmetic type A from the populations (p) and
 // d = feq - g in T; x_i = d_i / g_i is formed on the fly in A (twice: for
 // the Omega+- sums and for the Omega+ fractions of b), so d stays intact and
 // no Q-array of A is live.  One reciprocal per population serves c1 and c
 // together.  Returns alpha before the guard and x_min in xmin.
-template <int D, typename T, typename A, int MODE, bool SH>
-__device__ __attribute__((always_inline)) inline A alpha_exact(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], A beta, A &xmin)
+template <int D, typename T, typename A, int MODE, bool SH, typename P>
+__device__ __attribute__((always_inline)) inline A alpha_exact(const P &p, const T (&d)[Lat<D>::Q], A beta, A &xmin)
 {
     constexpr int Q = Lat<D>::Q;
     A S2 = 0, M3 = 0, M4 = 0, M5 = 0, M6 = 0, C1 = 0, C = 0;
@@ -578,8 +605,8 @@ __device__ inline T phi_(T y, T l)
 // Iterate1 mode).  Returns alpha_Lower, with info.fallback set, where the
 // result is not a mirror path length in (1, a*): no root (the mirror leaves
 // the polytope) or a step outside the interval.
-template <int D, typename T, typename A, bool SH, bool FULL>
-__device__ __attribute__((always_inline)) inline A mirror_alpha(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], A aL, A xmin, CellInfo &info)
+template <int D, typename T, typename A, bool SH, bool FULL, typename P>
+__device__ __attribute__((always_inline)) inline A mirror_alpha(const P &p, const T (&d)[Lat<D>::Q], A aL, A xmin, CellInfo &info)
 {
     constexpr int Q = Lat<D>::Q;
     auto xof = [&](int i) { return A(d[i]) * rcp_(A(gval<D, T, SH>(i, p))); };
@@ -628,12 +655,15 @@ __device__ __attribute__((always_inline)) inline A mirror_alpha(const T (&p)[Lat
 // cell whose x reach beyond the series bound has populations far from the
 // equilibrium, and the update multiplies an error of alpha by x relative to
 // g: double sums there keep that product below the storage rounding).
-template <int D, typename T, typename A, int MODE, bool SH>
-__device__ __attribute__((always_inline)) inline T path_length(const T (&p)[Lat<D>::Q], const T (&d)[Lat<D>::Q], double beta64, CellInfo &info)
+template <int D, typename T, typename A, int MODE, bool SH, typename SC = SeriesCfg<T>, typename P>
+__device__ __attribute__((always_inline)) inline T path_length(const P &p, const T (&d)[Lat<D>::Q], double beta64, CellInfo &info)
 {
     constexpr int Q = Lat<D>::Q;
     const T beta = T(beta64);
-    constexpr int K = SeriesCfg<T>::K;
+    constexpr int K = SC::K;
+    // moment arrays reach index 6 at least (a takes N_3..N_6; those beyond K
+    // stay zero)
+    constexpr int KA = K < 6 ? 6 : K;
     info.gated = 0;
     info.guarded = 0;
     info.exact = 0;
@@ -647,9 +677,9 @@ __device__ __attribute__((always_inline)) inline T path_length(const T (&p)[Lat<
     // Tm[k] = <g, x^k> = sum d x^(k-1) (k = 2..K) and Nm[k] = <g, x^k>_-
     // (k = 3..K), the latter with min(d, 0) = d on Omega- (g > 0)
     T xmin = T(0), xabs = T(0);
-    T Tm[K + 1], Nm[K + 1];
+    T Tm[KA + 1], Nm[KA + 1];
 #pragma unroll
-    for (int k = 0; k <= K; ++k) Tm[k] = Nm[k] = T(0);
+    for (int k = 0; k <= KA; ++k) Tm[k] = Nm[k] = T(0);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
         const T x = d[i] * rcp_(gval<D, T, SH>(i, p));
@@ -679,7 +709,7 @@ __device__ __attribute__((always_inline)) inline T path_length(const T (&p)[Lat<
     if (xabs < T(kGate)) {
         alpha = T(2);  // near-equilibrium gate (App. D)
         info.gated = 1;
-    } else if (xabs < T(SeriesCfg<T>::X)) {
+    } else if (xabs < T(SC::X)) {
         // series of 2x^2/(2+x), x^2 N3/P3 and R(y); coefficients for x^2..x^8
         // and y^0..y^5 (exact rationals)
         constexpr double c1k[7] = {1.0, -0.5, 0.25, -0.125, 0.0625, -0.03125, 0.015625};

@@ -128,35 +128,73 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
 //    gated cell would shift the viscosity of the whole flow by its relative
 //    rounding, visible above the shifted floor;
 //  - F16-shifted: storage rounding (1e-3 of the deviation) dwarfs all
-//    arithmetic rounding; F64: every part is double already.
+//    arithmetic rounding, and the power series of the path-length sums is
+//    cut at the order that rounding allows (SeriesCfgF16); F64: every part
+//    is double already.
 // The kernel is a stream of Q loads and Q stores per lane and needs several
 // waves per SIMD in flight to cover HBM latency: 4 waves (<= 128 VGPRs) for
 // the 4- and 2-byte formats; the double moments and equilibrium of
 // F32-shifted fit there too without scratch on the common path.
+//
+// Double precision: the Q stored values alone take 54 VGPRs in D3Q27, and
+// with d and the path-length sums the step needs about 210, i.e. two waves
+// per SIMD, too few to hide the memory latency behind its arithmetic (about
+// 1,900 VALU issue slots per wave).  The periodic closed-form steps
+// therefore park 24 of the 27 stored values in LDS once the moments are
+// formed (stash = 24: 48 KiB per 256-lane block, three blocks per CU) and
+// run at three waves (stash_waves): 1.44-1.50 -> 1.38 ms at 256^3.
 template <typename S>
 struct StepPolicy {
     static constexpr int waves = 4;
     static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
+    static constexpr int stash = 0, stash_waves = 0;
+    using Series = SeriesCfg<typename Storage<S>::T>;
     using Exact = double;
 };
 template <>
 struct StepPolicy<f32s> {
     static constexpr int waves = 4;
     static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = true;
+    static constexpr int stash = 0, stash_waves = 0;
+    using Series = SeriesCfg<float>;
     using Exact = double;
 };
 template <>
 struct StepPolicy<_Float16> {
     static constexpr int waves = 4;
     static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
+    static constexpr int stash = 0, stash_waves = 0;
+    using Series = SeriesCfgF16;
     using Exact = float;
 };
 template <>
 struct StepPolicy<double> {
     static constexpr int waves = 2;
     static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = false;
+    static constexpr int stash = 24, stash_waves = 3;
+    using Series = SeriesCfg<double>;
     using Exact = double;
 };
+
+// a if A, else b (both by reference)
+template <bool A, typename X, typename Y>
+__device__ inline const auto &pick(const X &a, const Y &b)
+{
+    if constexpr (A) return a;
+    else return b;
+}
+
+// Stored values a step parks in LDS (PopAccess): the policy's count for the
+// periodic two-lattice D3Q27 steps with a closed-form path length; none for
+// alpha = 2 (BGK fits two waves' registers and is memory-bound there: parked
+// at three waves it measured 2% slower), the in-place halves (parked at
+// three waves, 3-5% slower than at two), and the walled, ES-BGK and
+// mirror-condition steps, which keep their own occupancy.
+template <int D, typename S, int MODE, bool WALL, bool QE, int AA>
+constexpr int stash_pops()
+{
+    return (D == 3 && !WALL && !QE && AA == 0 && (MODE == MODE_HIGHER || MODE == MODE_LOWER)) ? StepPolicy<S>::stash : 0;
+}
 
 // d = feq - g of one cell, with moments and equilibrium in EQ, rounded to T,
 // and its mass and momentum then made exact to rounding.
@@ -215,11 +253,12 @@ constexpr int step_waves_qe()
 // The forced step evaluates two more equilibria (at u and u + F/rho) while d
 // and the stored values are live: at the periodic step's four waves its
 // common path would spill, so it runs at three.
-template <int D, typename S, int MODE, bool WALL, bool QE, bool FORCE>
+template <int D, typename S, int MODE, bool WALL, bool QE, bool FORCE, int AA>
 constexpr int step_waves_k()
 {
-    return WALL ? (is_mirror_mode(MODE) ? 1 : (step_waves_qe<D, S, MODE, QE>() > 3 ? 3 : step_waves_qe<D, S, MODE, QE>()))
-                : (FORCE && step_waves_qe<D, S, MODE, QE>() > 3 ? 3 : step_waves_qe<D, S, MODE, QE>());
+    return stash_pops<D, S, MODE, WALL, QE, AA>() > 0 ? StepPolicy<S>::stash_waves
+           : WALL ? (is_mirror_mode(MODE) ? 1 : (step_waves_qe<D, S, MODE, QE>() > 3 ? 3 : step_waves_qe<D, S, MODE, QE>()))
+                  : (FORCE && step_waves_qe<D, S, MODE, QE>() > 3 ? 3 : step_waves_qe<D, S, MODE, QE>());
 }
 
 // Pull with diffuse walls (the boundary rule of the lid-driven cavity,
@@ -345,7 +384,7 @@ __device__ inline void fix_x_wall(const StepArgs &a, long long cell, typename St
 enum AAKind { kTwoLattice = 0, kAAPull = 1, kAALocal = 2 };
 
 template <int D, typename S, int MODE, bool DIAG, bool FORCE, bool WALL = false, bool QE = false, int AA = kTwoLattice>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_k<D, S, MODE, WALL, QE, FORCE>()))) void k_step(StepArgs a)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_k<D, S, MODE, WALL, QE, FORCE, AA>()))) void k_step(StepArgs a)
 {
     using T = typename Storage<S>::T;
     using Pol = StepPolicy<S>;
@@ -360,6 +399,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
     InP fin = (const S *)a.fin;
     OutP fout = (S *)a.fout;
     const T beta = (T)a.beta;
+    // the LDS columns of the stored values a double-precision step parks
+    __shared__ T stash[stash_pops<D, S, MODE, WALL, QE, AA>() > 0 ? stash_pops<D, S, MODE, WALL, QE, AA>() * kStashStride : 1];
 
     LaneStats ls;
     if (x < nx) {
@@ -423,6 +464,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
         bool pos = true;
 #pragma unroll
         for (int i = 0; i < Q; ++i) pos = pos && (gval<D, T, SH>(i, p) > T(0));
+        // from here on the stored values are read through pa: in registers,
+        // or mostly parked in LDS (the empty asm's memory clobber keeps the
+        // compiler from forwarding the parked registers to their reads)
+        constexpr int NST = stash_pops<D, S, MODE, WALL, QE, AA>();
+        PopAccess<T, Q, (NST > 0 ? NST : 1)> parked;
+        if constexpr (NST > 0) {
+#pragma unroll
+            for (int i = 0; i < NST; ++i) stash[i * kStashStride + threadIdx.x] = p[i];
+            asm volatile("" ::: "memory");
+            parked.col = &stash[threadIdx.x];
+#pragma unroll
+            for (int i = NST; i < Q; ++i) parked.tail[i - NST] = p[i];
+        }
+        const auto &pa = pick<NST == 0>(p, parked);
+        auto pdev = [&](int i) { return SH ? pa[i] : pa[i] - T(Lat<D>::w(i)); };
         const T drho = T(drhoE);
         const T j[3] = {T(jE[0]), T(jE[1]), T(jE[2])};
         // NaN in any population fails its comparison and propagates into drho.
@@ -446,13 +502,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
             // fixed function of the cell's state, so it acts as a bias that
             // accumulates over steps.  The path length stays in T.
             using EQ = typename std::conditional<Pol::eq_f64, double, T>::type;
-            form_deviation<D, T, EQ, MODE == MODE_LBGK>(dev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
+            form_deviation<D, T, EQ, MODE == MODE_LBGK>(pdev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
             // ES-BGK: the quasi-equilibrium replaces the equilibrium, and the
             // path length is found from x = f^QE / g - 1 as before
             int qe_it = 0;
             bool qe_ok = true;
             if constexpr (QE) qe_ok = quasi_equilibrium<D, T, EQ, SH>(p, dd, EQ(a.cpr), qe_it);
-            alpha = path_length<D, T, typename Pol::Exact, MODE, SH>(p, dd, a.beta, info);
+            alpha = path_length<D, T, typename Pol::Exact, MODE, SH, typename Pol::Series>(pa, dd, a.beta, info);
             if constexpr (QE) {
                 info.iters = qe_it;
                 info.fallback = !qe_ok;
@@ -483,7 +539,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
         // post-collision value p + alpha beta (feq - g) [+ force term]
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            const T v = Pol::ab_split || FORCE ? fma_(ab, dd[i], fma_(ab_lo, dd[i], p[i])) : fma_(ab, dd[i], p[i]);
+            const T v = Pol::ab_split || FORCE ? fma_(ab, dd[i], fma_(ab_lo, dd[i], pa[i])) : fma_(ab, dd[i], pa[i]);
             if constexpr (AA == kAAPull) {
                 // slot opp(i) of cell x + c_i, the location this lane read
                 // population opp(i) from
@@ -493,6 +549,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
                 S *orow = fout + ((long long)i * N + row0);
                 Storage<S>::store_nt(lane_ptr(orow, (unsigned)x), v);
             }
+        }
+
+        // the velocity and density of the output state, for a loss that
+        // depends on f through them: u = (sum_i c_i f_out,i + F/2) / rho,
+        // where the output's momentum is j, plus F in a collided forced cell
+        // (the force term adds F exactly); formed here from the moments the
+        // step already holds, in place of a pass that re-reads the state
+        if ((DIAG || FORCE) && a.uv_out) {
+            const T r = T(1) + drho, ir = rcp_(r);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                T jc = j[c];
+                if (FORCE) jc += (ok ? T(1.5) : T(0.5)) * (T)a.force[(long long)c * N + cell];
+                a.uv_out[(long long)c * N + cell] = (float)quot_(jc, r, ir);
+            }
+            a.uv_out[(long long)D * N + cell] = (float)r;
         }
 
         if (DIAG) {

@@ -60,6 +60,7 @@ _SIGNATURES = {
     "eselbm_set_stats": [_vp, ctypes.c_int],
     "eselbm_set_alpha_field": [_vp, _vp],
     "eselbm_set_nut_field": [_vp, _vp],
+    "eselbm_set_velocity_field": [_vp, _vp],
     "eselbm_set_force": [_vp, _vp],
     "eselbm_set_walls": [_vp, ctypes.c_int, _vp],
     "eselbm_set_prandtl": [_vp, ctypes.c_double],
@@ -72,6 +73,7 @@ _SIGNATURES = {
     "eselbm_kinetic_loss_noalloc": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
     "eselbm_dissipation_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_dissipation_seed": [_vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "eselbm_dissipation_loss_uv": [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_equilibrium_vjp": [_vp, _vp, _vp, _vp, _vp, _vp],
 }
 EXPORTS = tuple(_SIGNATURES) + ("eselbm_last_error",)
@@ -155,6 +157,7 @@ class Solver:
         self._alpha = None
         self._nut = None
         self._force = None
+        self._uv = None
         self.set_mode(mode)
 
     def __del__(self):
@@ -194,6 +197,16 @@ class Solver:
         self._nut = nut
         with self._on():
             _check(lib.eselbm_set_nut_field(self._h, self._p(nut, self.compute_dtype, self.cells)))
+
+    def set_velocity_field(self, uv: torch.Tensor | None):
+        """Register a [D + 1, *shape] float32 tensor receiving u (with the
+        half-force shift) and rho of each step call's output state."""
+        self._uv = uv
+        with self._on():
+            _check(lib.eselbm_set_velocity_field(self._h, self._p(uv, torch.float32, (self.D + 1) * self.cells)))
+
+    def empty_velocity(self) -> torch.Tensor:
+        return torch.empty((self.D + 1,) + self.shape, dtype=torch.float32, device=self.device)
 
     def set_walls(self, walls=None, velocity=None):
         """Diffuse walls: ``walls`` per axis (x, y[, z]) True/False (None: none);
@@ -310,6 +323,20 @@ class Solver:
             _check(lib.eselbm_dissipation_seed(
                 self._h, self._p(f, self.storage_dtype, self.Q * self.cells),
                 self._p(seed, self.compute_dtype, (1 + self.D) * self.cells), float(weight),
+                self._p(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+                _stream(stream)))
+
+    def dissipation_loss_uv(self, uv, loss=None, lam=None, seed=None, weight: float = 1.0, force_grad=None,
+                            stream=None):
+        """dissipation_loss / dissipation_seed from a velocity field written
+        by a step (set_velocity_field) instead of the state."""
+        with self._on():
+            _check(lib.eselbm_dissipation_loss_uv(
+                self._h, self._p(uv, torch.float32, (self.D + 1) * self.cells),
+                self._p(loss, torch.float64, 1) if loss is not None else _vp(None),
+                self._p(lam, self.compute_dtype, self.Q * self.cells) if lam is not None else _vp(None),
+                self._p(seed, self.compute_dtype, (1 + self.D) * self.cells) if seed is not None else _vp(None),
+                float(weight),
                 self._p(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
                 _stream(stream)))
 

@@ -195,6 +195,58 @@ def test_adjoint_degenerate_and_ragged_grids(es, D, shape, dtype):
     assert err < (1e-11 if dtype == "f64" else 1e-4)
 
 
+@pytest.mark.parametrize("dtype,forced,in_place", [("f32", True, False), ("f32", True, True), ("f32", False, False),
+                                                   ("f64", False, False), ("f32s", False, False)])
+def test_velocity_field_of_the_step(es, dtype, forced, in_place):
+    """The velocity and density field a step writes (set_velocity_field)
+    against the FP64 moments of its output state (eselbm_moments, the
+    half-force shift included), and the dissipation loss and seeds formed from
+    it against those formed from the state."""
+    shape = (6, 9, 70)
+    f0 = _state(3, shape, 6, 2e-3)
+    s = es.Solver("D3Q27", shape, dtype=dtype)
+    if forced:
+        s.set_force(_t(W.random_force(shape, 3, amplitude=1e-3, seed=8)).float().cuda())
+    a = _t(f0).to(s.storage_dtype).cuda() if dtype != "f32s" else _t(f0 - oracle.lattice(3)[1][:, None, None, None]).float().cuda()
+    uv = s.empty_velocity()
+    s.set_velocity_field(uv)
+    if in_place:
+        b = a
+        s.step(a, a, 2, 2e-3)
+    else:
+        b = s.empty_state()
+        s.step(a, b, 1, 2e-3)
+    s.set_velocity_field(None)
+    rho, u = s.moments(b)
+    torch.cuda.synchronize()
+    du = float((uv[:3].double() - u).abs().max()) / float(u.abs().max())
+    dr = float((uv[3].double() - rho).abs().max())
+    w = 0.3
+    l1 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    l2 = torch.zeros(1, dtype=torch.float64, device="cuda")
+    s1, s2 = s.empty_seed(), s.empty_seed()
+    g1 = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda") if forced else None
+    g2 = torch.zeros((3,) + shape, dtype=torch.float32, device="cuda") if forced else None
+    s.dissipation_loss(b, loss=l1, weight=w)
+    s.dissipation_seed(b, s1, weight=w, force_grad=g1)
+    s.dissipation_loss_uv(uv, loss=l2, seed=s2, weight=w, force_grad=g2)
+    torch.cuda.synchronize()
+    dl = abs(l1.item() - l2.item()) / abs(l1.item())
+    ds = float((s1 - s2).abs().max()) / float(s1.abs().max())
+    msg = f"[velocity field {dtype} forced={forced} in_place={in_place}] u {du:.2e} rho {dr:.2e} loss {dl:.2e} seed {ds:.2e}"
+    if forced:
+        dg = float((g1 - g2).abs().max()) / float(g1.abs().max())
+        msg += f" dF {dg:.2e}"
+        assert dg < 1e-5
+    _log(msg)
+    # the field is formed from the step's own moments in single precision; the
+    # FP64 moments read the stored output, whose rounding (plain F32: about
+    # sqrt(Q) half-ulps of the populations) they sum as well
+    tol = 5e-6 if dtype == "f32" else 1e-6
+    assert du < tol and dr < tol
+    assert dl < 1e-5 and ds < 1e-5
+
+
 def test_kinetic_and_dissipation_seeds(es):
     shape = (6, 7, 9)
     f0 = _state(3, shape, 5, 1e-3)
