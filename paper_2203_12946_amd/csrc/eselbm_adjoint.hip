@@ -540,19 +540,32 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
         auto passes = [&](auto &&dirxd, auto guard) {
             constexpr bool keep_mu = !std::is_same<T, double>::value;
             constexpr bool GUARD = decltype(guard)::value;
+            // rho_bar += sum_i xd_i P_i and u_bar += sum_i xd_i dP_i/du,
+            // contracted one x-row (three populations, c_x = -1, 0, 1) at a
+            // time through the product form P_i = F_x F_y F_z, as contract_eq
+            // does for lambda
 #pragma unroll
-            for (int i = 0; i < Q; ++i) {
-                T dir, xd;
-                const T xi = xcopy(i);
-                dirxd(xi, dir, xd);
-                if (GUARD && i == imin) xd = xdmin;
-                T gp[3];
-                const T Pi = prod_and_grad<D, T>(i, F, dF, gp);
-                rhob = fma_(xd, Pi, rhob);
+            for (int r = 0; r < Q / 3; ++r) {
+                T xdr[3];
 #pragma unroll
-                for (int c = 0; c < D; ++c) ub[c] = fma_(xd, gp[c], ub[c]);
-                if constexpr (keep_mu) v[i] = fma_(-(T(1) + xi), xd, dir);
-                __builtin_amdgcn_sched_barrier(0);
+                for (int cx = 0; cx < 3; ++cx) {
+                    const int i = 3 * r + cx;
+                    T dir, xd;
+                    const T xi = xcopy(i);
+                    dirxd(xi, dir, xd);
+                    if (GUARD && i == imin) xd = xdmin;
+                    xdr[cx] = xd;
+                    if constexpr (keep_mu) v[i] = fma_(-(T(1) + xi), xd, dir);
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+                const int fy = r % 3, fz = r / 3;  // c_y + 1, c_z + 1 of row r
+                const T ra = fma_(xdr[0], F[0][0], fma_(xdr[1], F[0][1], xdr[2] * F[0][2]));
+                const T rb = fma_(xdr[0], dF[0][0], fma_(xdr[1], dF[0][1], xdr[2] * dF[0][2]));
+                const T fzv = D == 3 ? F[2][fz] : T(1);
+                rhob = fma_(ra, F[1][fy] * fzv, rhob);
+                ub[0] = fma_(rb, F[1][fy] * fzv, ub[0]);
+                ub[1] = fma_(ra, dF[1][fy] * fzv, ub[1]);
+                if (D == 3) ub[2] = fma_(ra, F[1][fy] * dF[2][fz], ub[2]);
             }
             // feq = rho P(u): dfeq/du = rho dP/du; the force term's u_f; then
             // u = j / rho
