@@ -47,7 +47,7 @@ METRIC = "ESELBM MLUPS & % HBM roofline (D3Q27 FP32 vs FP64); adjoint/forward ti
 KERNEL_SOURCES = ["paper_2203_12946_amd/csrc/step_kernel.hpp", "paper_2203_12946_amd/csrc/step_f32.hip",
                   "paper_2203_12946_amd/csrc/lattice.hpp", "paper_2203_12946_amd/csrc/quasi_eq.hpp"]
 TRAFFIC_FILE = ROOT / "profiles" / "traffic_d3q27_f32_256.md"
-VALU_FILE = ROOT / "profiles" / "valu_issue_d3q27_f32.md"
+VALU_FILE = ROOT / "profiles" / "valu_issue_d3q27.md"
 # VALU issue peak: 1024 SIMD16s at 2.4 GHz, 4 cycles per wave64 instruction
 VALU_WAVE_INSTR_PER_S = 256 * 4 * 2.4e9 / 4
 
@@ -82,14 +82,17 @@ def alu_roofline(kernel_ms: float):
     """Second roofline of the headline step: its measured VALU issue slots per
     launch (committed counter summary) at the chip's issue rate, against the
     kernel time; None once the kernel sources have changed.  A wave64 VALU
-    instruction occupies its SIMD16 for 4 cycles; a transcendental one
-    (reciprocal, square root, logarithm, exponential: quarter rate) for 16,
-    so each counts as 4 issue slots."""
+    instruction occupies its SIMD16 for one 4-cycle issue slot; the
+    transcendental ones (reciprocal, square root) take more.  The issue slots
+    are the hardware's own count, SQ_ACTIVE_INST_VALU per wave (it reads one
+    slot per instruction plus one per single-precision transcendental);
+    without it, VALU + 3 x transcendental instructions bound them from
+    above."""
     kv = _profile_values(VALU_FILE)
     if kv is None:
         return None
     valu, trans = float(kv["valu_per_wave"]), float(kv.get("trans_per_wave", 0.0))
-    slots = valu + 3.0 * trans
+    slots = float(kv["active_valu_per_wave"]) if "active_valu_per_wave" in kv else valu + 3.0 * trans
     floor_ms = slots * float(kv["waves_per_launch"]) / VALU_WAVE_INSTR_PER_S * 1e3
     return {"bound": "alu", "issue_floor_ms": round(floor_ms, 4), "kernel_ms": round(kernel_ms, 4),
             "frac": round(floor_ms / kernel_ms, 4), "valu_per_wave": valu, "trans_per_wave": trans,
@@ -311,9 +314,13 @@ def time_adjoint_2d(es, torch, W):
         return t1 - t0, t2 - t1, float(L.item()), u0.grad
 
     run()  # warm-up
-    fwd, bwd, L, g = run()
+    # a few milliseconds each, launch-bound: the median of five runs
+    runs = [run() for _ in range(5)]
+    fwd = sorted(r[0] for r in runs)[2]
+    bwd = sorted(r[1] for r in runs)[2]
+    L, g = runs[-1][2], runs[-1][3]
     return dict(workload=wl.name, steps=wl.steps, ckpt_every=20, forward_s=fwd, backward_s=bwd,
-                ratio=bwd / fwd, loss=L, grad_finite=bool(torch.isfinite(g).all().item()))
+                ratio=bwd / fwd, loss=L, grad_finite=bool(torch.isfinite(g).all().item()), timing="median of 5")
 
 
 def cpu_baseline(W, wl, seconds_target: float = 10.0):
@@ -570,6 +577,12 @@ def main():
                      "frac_of_bgk": round(bgk["kernel_ms"] / main_run["kernel_ms"], 4),
                      "copy_calibration_gbs": round(copy_gbs, 1)},
         "alu_roofline": alu_roofline(main_run["kernel_ms"]),
+        # which storage meets the stated parity bar (rho, u within 1e-6 of the
+        # FP64 oracle after 1000 steps), and at what fraction of HBM peak
+        "parity_1e-6": {"storage": "f32s", "note": "F32 deviations f - w with FP64 moments and equilibrium; plain F32 "
+                                                   "storage rounding alone exceeds 1e-6 on u after 1000 steps",
+                        "frac": variants.get("f32s_higher", {}).get("frac"),
+                        "kernel_ms": variants.get("f32s_higher", {}).get("kernel_ms")},
         "cpu_baseline": cpu,
         "variants": variants,
         "adjoint": adj,

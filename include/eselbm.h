@@ -241,7 +241,11 @@ eselbm_status eselbm_init_equilibrium(eselbm_handle h, const double *rho, const 
 
 /* Runs nsteps >= 1 pull-stream + collide steps.
  * f_in holds the initial state; the result is in f_out.  For nsteps > 1,
- * f_in is the ping-pong partner and is overwritten.  f_in and f_out must
+ * f_in is the ping-pong partner and is overwritten.  On two lattices the
+ * steps alternate f_in -> f_out -> f_in, so after an even nsteps the newest
+ * state is in f_in and one device-to-device copy of a state (bandwidth-bound,
+ * about the cost of one step) moves it to f_out; odd counts, or in-place
+ * stepping, need no copy.  f_in and f_out must
  * be distinct, non-overlapping buffers of Q * n_cells storage elements, or
  * the same buffer: then the steps run in place on that one lattice (the
  * AA pattern: odd steps pull from the neighbours and write each population
