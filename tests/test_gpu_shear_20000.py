@@ -103,8 +103,9 @@ def test_shear_layer_20000_steps_vs_oracle_checkpoints():
     cells.  FP64 is held to 1e-9 in u pointwise throughout (the roll-up
     amplifies rounding to about 2e-10 by step 20000); the 4-byte formats to
     their 1000-step storage bars pointwise at step 1000 and to their kinetic
-    energy and mass bars at every checkpoint, the pointwise drift beyond
-    being reported."""
+    energy bars at every checkpoint, the pointwise drift beyond being
+    reported; mass is held to its conservation bars against the initial
+    mass."""
     import json
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
@@ -113,6 +114,7 @@ def test_shear_layer_20000_steps_vs_oracle_checkpoints():
     wl = W.SHEAR_1024
     assert tuple(ref["steps"]) == CHECKPOINTS and abs(ref["tau"] - wl.tau) < 1e-15
     rho0, u0 = W.fields_for(wl)
+    mass0 = float(np.sum(rho0))
     ys = np.array([c[0] for c in ref["cells"]])
     xs = np.array([c[1] for c in ref["cells"]])
     ke_tol = {"f64": 1e-10, "f32s": 1e-6, "f32": 1e-5}
@@ -136,7 +138,10 @@ def test_shear_layer_20000_steps_vs_oracle_checkpoints():
             dr_cells = float(np.max(np.abs(r[ys, xs] - np.array(cp["rho"]))))
             dke = abs(ke - cp["kinetic"]) / cp["kinetic"]
             dul2 = abs(float(np.linalg.norm(v)) - cp["u_l2"]) / cp["u_l2"]
-            dm = abs(mass - cp["mass"]) / cp["mass"]
+            # mass against the initial mass: the step conserves it to its own
+            # rounding, the oracle (no conservation fix) drifts by 2e-12 over
+            # the run
+            dm = abs(mass - mass0) / mass0
             _log(f"[shear 20000 vs stored oracle] step {c:5d} {dtype:4s}: cells max|du|={du_cells:.2e} "
                  f"max|drho|={dr_cells:.2e} rel|dKE|={dke:.2e} rel|d|u|_2|={dul2:.2e} mass {dm:.2e}")
             assert np.all(np.isfinite(v))
