@@ -204,27 +204,38 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
         const unsigned hi = (unsigned)__builtin_amdgcn_readfirstlane((int)(unsigned)(u >> 32));
         return (long long)(((unsigned long long)hi << 32) | lo);
     };
-    // lambda_i of the state after the step, plus the optional loss seed of
-    // that state, s0 + c_i . s (affine in the velocity: the seeds of losses
-    // that depend on f through rho and u only)
-    T sd[4] = {T(0), T(0), T(0), T(0)};
+    // lambda_i of the state after the step
+    auto lam_at = [&](int i) { return *lane_ptr(lin + uniform((long long)i * N + row0), (unsigned)x); };
+    // The optional loss seed of that state, s0 + c_i . s, adds to lambda
+    // (affine in the velocity: the seeds of losses that depend on f through
+    // rho and u only).  The collision conserves mass and momentum and the
+    // force adds F independently of g (sum_i f*_i = rho, sum_i c_i f*_i =
+    // j + F), so such a seed passes through the step's VJP unchanged: it
+    // adds s0 + c_i . s to mu_i and s to dL/dF, and nothing to alpha_bar or
+    // to the equilibrium's adjoint.  It is therefore not added to lambda
+    // but once, to the adjoints of rho and j below.
+    // The seed is read here, at the start, so that its latency hides behind
+    // the pulls; without a seed the loads read lambda (Q >= D + 1 planes) and
+    // are discarded, so that no branch splits the code.
     const T *seed = (const T *)a.seed;
-    if (seed) {
+    T sd[4];
+    {
+        const T *sp = seed ? seed : lin;
 #pragma unroll
-        for (int c = 0; c <= D; ++c) sd[c] = seed[(long long)c * N + row0 + x];
-    }
-    auto lam_at = [&](int i) {
-        T v = *lane_ptr(lin + uniform((long long)i * N + row0), (unsigned)x);
-        if (seed) {
-            v += sd[0];
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                if (Lat<D>::c(i, c) > 0) v += sd[1 + c];
-                if (Lat<D>::c(i, c) < 0) v -= sd[1 + c];
-            }
+        for (int c = 0; c < 4; ++c) {
+            const T sv = c <= D ? sp[(long long)c * N + row0 + x] : T(0);
+            sd[c] = seed ? sv : T(0);
         }
-        return v;
-    };
+    }
+    // the force gradient accumulated so far, read at the start for the same
+    // reason (its read-modify-write is each lane's own cell); without a
+    // gradient buffer the force itself (same size) is read and discarded
+    float fg0[3] = {0.f, 0.f, 0.f};
+    if (FORCE) {
+        const float *fp = a.force_grad ? a.force_grad : a.force;
+#pragma unroll
+        for (int c = 0; c < D; ++c) fg0[c] = fp[(long long)c * N + row0 + x];
+    }
     // adjoint of the pull: lam_n_i(x - c_i) = mu_i(x)
     auto push = [&](int i, T m) { *lane_ptr(lout + uniform((long long)i * N + pix.src_row(i)), pix.src_x(i)) = m; };
 
@@ -506,15 +517,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
 #pragma unroll
         for (int c = 0; c < 3; ++c) ub[c] = lfac * slg[c];
         T ubf[3] = {T(0), T(0), T(0)};
+        // The loss seed of the state after the step (sd) must end as
+        // j_bar += s and rho_bar += s0.  The chain rule through u = j / rho
+        // below forms j_bar = (rho ub + ubf) / rho and takes
+        // (rho ub + ubf) . u / rho from rho_bar, so rho s goes into ubf and
+        // s0 + s . u into rho_bar here.
+#pragma unroll
+        for (int c = 0; c < D; ++c) rhob = fma_(sd[1 + c], u[c], rhob);
+        rhob += sd[0];
         if (FORCE) {
 #pragma unroll
             for (int c = 0; c < D; ++c) {
                 const T fb = rho * slfg[c];
                 ubf[c] = fb;
                 rhob -= fb * Fc[c] * ir * ir;
-                if (a.force_grad) a.force_grad[(long long)c * N + row0 + x] += (float)(fb * ir);
+                if (a.force_grad) a.force_grad[(long long)c * N + row0 + x] = fg0[c] + (float)(fb * ir + sd[1 + c]);
             }
         }
+#pragma unroll
+        for (int c = 0; c < D; ++c) ubf[c] = fma_(rho, sd[1 + c], ubf[c]);
 
         // Per population, (dir, xd): the explicit g-derivative of the
         // path-length sums at fixed x, and their x-derivative over g (the
@@ -576,6 +597,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
                 jb[c] = uc * ir;
                 rhob -= uc * u[c] * ir;
             }
+            // rho_bar + c_i . j_bar, the y and z parts once per x-row
+            T base[Q / 3];
+#pragma unroll
+            for (int r = 0; r < Q / 3; ++r) {
+                T bs = rhob;
+                const int cy = r % 3 - 1, cz = r / 3 - 1;
+                if (cy > 0) bs += jb[1];
+                if (cy < 0) bs -= jb[1];
+                if (D == 3 && cz > 0) bs += jb[2];
+                if (D == 3 && cz < 0) bs -= jb[2];
+                base[r] = bs;
+            }
             // the second read of lambda (the empty asm with a memory clobber
             // keeps the compiler from reusing the first)
             asm volatile("" ::: "memory");
@@ -585,19 +618,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
             for (int i = 0; i < Q; ++i) {
                 T m;
                 if constexpr (keep_mu) {
-                    m = fma_(l[i], T(1) - ab, v[i]) + rhob;
+                    m = fma_(l[i], T(1) - ab, v[i]) + base[i / 3];
                 } else {
                     T dir, xd;
                     const T xi = xcopy(i);
                     dirxd(xi, dir, xd);
                     if (GUARD && i == imin) xd = xdmin;
-                    m = fma_(l[i], T(1) - ab, dir) - (T(1) + xi) * xd + rhob;
+                    m = fma_(l[i], T(1) - ab, dir) - (T(1) + xi) * xd + base[i / 3];
                 }
-#pragma unroll
-                for (int c = 0; c < D; ++c) {
-                    if (Lat<D>::c(i, c) > 0) m += jb[c];
-                    if (Lat<D>::c(i, c) < 0) m -= jb[c];
-                }
+                if (Lat<D>::c(i, 0) > 0) m += jb[0];
+                if (Lat<D>::c(i, 0) < 0) m -= jb[0];
                 push(i, m);
                 __builtin_amdgcn_sched_barrier(0);
             }
@@ -659,9 +689,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
             }, std::false_type{});
         }
     } else {
-        // uncollided cell: out = g, so mu = lambda
+        // uncollided cell: out = g, so mu = lambda (with the seed); lambda
+        // as read at the start, so that its loads are issued with the pulls
+        // on both sides of the branch
 #pragma unroll
-        for (int i = 0; i < Q; ++i) push(i, lam_at(i));
+        for (int i = 0; i < Q; ++i) {
+            T m = l[i] + sd[0];
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                if (Lat<D>::c(i, c) > 0) m += sd[1 + c];
+                if (Lat<D>::c(i, c) < 0) m -= sd[1 + c];
+            }
+            push(i, m);
+        }
     }
 }
 
@@ -780,7 +820,9 @@ static hipError_t ensure_scratch(LossScratch &sc, const Grid &g)
     if (e == hipSuccess) e = hipMalloc((void **)&sc.vort, sizeof(float) * 3 * g.N);
     if (e == hipSuccess) e = hipMalloc((void **)&sc.part, sizeof(double) * parts);
     if (e != hipSuccess) {
-        free_loss_scratch(sc);
+        // the allocation error is the one reported; the release of what was
+        // allocated can only add the same out-of-memory state
+        (void)free_loss_scratch(sc);
         return e;
     }
     sc.cells = g.N;

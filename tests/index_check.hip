@@ -6,7 +6,8 @@
 // over every block, lane and population, and checks each access the
 // kernels make:
 //   - in bounds: every offset lies in its buffer (Q * N state or adjoint
-//     elements, (1 + D) * N seed values, D * N force values), and each lane's
+//     elements, (1 + D) * N seed values or, without a seed, the same offsets
+//     of lambda, D * N force values), and each lane's
 //     byte offset within a row fits the 32 bits the kernels add to the row's
 //     base;
 //   - a permutation where it must be one: the pull loads of the step (and the
@@ -96,7 +97,10 @@ static int run(int nx, int ny, int nz, bool full)
                         const long long o = (long long)c * N + pix.row0 + x;
                         if (o < 0 || o >= (long long)(1 + D) * N) return fail("seed", o, (1 + D) * N, x, y, z, c);
                         if (c < D && o >= (long long)D * N) return fail("force", o, D * N, x, y, z, c);
-                        checked += 1 + (c < D);
+                        // without a seed the adjoint reads lambda at these
+                        // offsets instead (and discards the values)
+                        if (o >= QN) return fail("seed read of lambda", o, QN, x, y, z, c);
+                        checked += 2 + (c < D);
                     }
                 }
     if (full) {
