@@ -284,7 +284,10 @@ def time_adjoint(es, torch, W, steps: int, ckpt: int):
     nu0 = wl.nu
     ro = Rollout(s, wl.tau, steps, ckpt, diss_weight=nu0)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    ro.forward(f0, loss)  # warm-up
+    # one untimed forward and backward each (first allocations of the
+    # caching allocator, the library's loss scratch)
+    ro.forward(f0, loss)
+    ro.backward(None, diss_grad=1.0, force_grad=torch.zeros((3,) + wl.shape, dtype=torch.float32, device="cuda"))
     torch.cuda.synchronize()
     loss.zero_()
     t0 = time.perf_counter()

@@ -325,8 +325,8 @@ eselbm_status eselbm_kinetic_loss_noalloc(eselbm_handle h, const void *f, double
  * force_grad (device float [D][cells]).  Any output may be NULL.  The loss
  * is summed in a fixed order (the same bits on every run).
  * Scratch: the first loss call on a handle allocates handle-owned device
- * fields of 7 floats per cell (u, rho, vorticity) and one double per 64-256
- * cells (partial sums) on the current device, kept until eselbm_destroy;
+ * fields of 4 floats per cell (u, rho) and one double per 64-256 cells
+ * (partial sums) on the current device, kept until eselbm_destroy;
  * loss calls on one handle share them, so such calls that overlap on
  * different streams race (use one handle per concurrent stream). */
 eselbm_status eselbm_dissipation_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam,

@@ -8,12 +8,17 @@ schedules them:
   weight * sum_x |omega|^2 after every step.  The step itself writes the
   velocity and density of its output (the loss depends on the state only
   through them), so the loss reads that field instead of the state.
+  The states of the last segment (those after its checkpoint) are written to
+  buffers of their own and kept, with their velocity fields, as is the
+  velocity field of every checkpoint: the backward sweep starts from them.
 * ``Rollout.backward`` sweeps the checkpoint segments in reverse.  For each
-  segment it recomputes the segment's states from its checkpoint (with their
-  velocity fields), then applies the adjoint step kernel from the last state
-  down to the first.  The per-step loss seeds travel in compact per-cell form
-  (dL/df_i = s0 + c_i.s) and each is added by the adjoint step that reads it.
-  The adjoint kernel also accumulates the body-force gradient.
+  segment but the last it recomputes the segment's states from its
+  checkpoint (with their velocity fields); the last segment's were kept by
+  the forward sweep.  It then applies the adjoint step kernel from the
+  segment's last state down to the first.  The per-step loss seeds travel in
+  compact per-cell form (dL/df_i = s0 + c_i.s) and each is added by the
+  adjoint step that reads it.  The adjoint kernel also accumulates the
+  body-force gradient.
 
 Autograd functions wrap the three pieces of a training objective:
 ``equilibrium`` (initial state from rho, u; gradient w.r.t. u), ``rollout``
@@ -38,6 +43,10 @@ class Rollout:
         self.K = int(ckpt_every)
         self.diss_weight = diss_weight
         self.ckpts: dict[int, torch.Tensor] = {}
+        # velocity fields of the checkpoints (with the loss), and the states
+        # of the last segment after its checkpoint with their velocity fields
+        self.ckpt_uv: dict[int, torch.Tensor] = {}
+        self.tail: dict[int, tuple[torch.Tensor, torch.Tensor | None]] = {}
         self.uv_end: torch.Tensor | None = None
 
     def _step_with_velocity(self, f: torch.Tensor, out: torch.Tensor, uv: torch.Tensor):
@@ -49,28 +58,47 @@ class Rollout:
         finally:
             s.set_velocity_field(None)
 
+    def _last_start(self) -> int:
+        """First state of the last checkpoint segment."""
+        return ((self.nsteps - 1) // self.K) * self.K
+
     def forward(self, f0: torch.Tensor, loss_acc: torch.Tensor | None = None) -> torch.Tensor:
         """State after nsteps; with a dissipation weight, adds the loss of
         every state f^1..f^n to ``loss_acc`` (a device float64 scalar)."""
         s = self.s
+        self.ckpts, self.ckpt_uv, self.tail, self.uv_end = {}, {}, {}, None
         cur = f0.clone()
         nxt = s.empty_state()
-        self.ckpts = {0: cur.clone()}
+        self.ckpts[0] = cur.clone()
         with_loss = self.diss_weight is not None and loss_acc is not None
         uv = s.empty_velocity() if with_loss else None
-        self.uv_end = None
+        last = self._last_start()
         for n in range(self.nsteps):
+            m = n + 1  # the state this step produces
+            # the states after the last checkpoint, and the final one, get
+            # buffers of their own (the former are kept for the backward)
+            fresh = m > last
+            keep = last < m < self.nsteps
+            out = s.empty_state() if fresh else nxt
+            out_uv = None
             if with_loss:
-                self._step_with_velocity(cur, nxt, uv)
+                out_uv = s.empty_velocity() if (keep or m == last) else uv
+                self._step_with_velocity(cur, out, out_uv)
+                s.dissipation_loss_uv(out_uv, loss=loss_acc, weight=self.diss_weight)
             else:
-                s.step(cur, nxt, 1, self.tau)
-            cur, nxt = nxt, cur
-            if with_loss:
-                s.dissipation_loss_uv(uv, loss=loss_acc, weight=self.diss_weight)
-            if (n + 1) % self.K == 0 and (n + 1) < self.nsteps:
-                self.ckpts[n + 1] = cur.clone()
+                s.step(cur, out, 1, self.tau)
+            if fresh:
+                cur = out
+            else:
+                cur, nxt = out, cur
+            if keep:
+                self.tail[m] = (out, out_uv)
+            if m % self.K == 0 and m < self.nsteps:
+                self.ckpts[m] = cur.clone()
+                if with_loss:
+                    self.ckpt_uv[m] = out_uv if m == last else out_uv.clone()
         if with_loss:
-            self.uv_end = uv
+            self.uv_end = out_uv
         return cur
 
     def backward(self, lam_final: torch.Tensor | None, diss_grad: float = 0.0,
@@ -96,19 +124,25 @@ class Rollout:
             else:
                 s.dissipation_seed(self._state_at_end(), seed, weight=w, force_grad=force_grad)
             pending = seed
-        seg_starts = sorted(self.ckpts)
-        for start in reversed(seg_starts):
+        last = self._last_start()
+        for start in sorted(self.ckpts, reverse=True):
             stop = min(start + self.K, n_end)
-            # states f^start .. f^(stop-1); with the loss, the velocity field
-            # of each recomputed one (the checkpoint's seed reads the state)
+            # states f^start .. f^(stop-1) and, with the loss, the velocity
+            # field of each (None where only the state is at hand)
             states = [self.ckpts[start]]
-            uvs = [None]
-            for _ in range(start, stop - 1):
+            uvs = [self.ckpt_uv.get(start)]
+            kept = start == last and all(m in self.tail for m in range(start + 1, stop))
+            for m in range(start + 1, stop):
+                if kept:
+                    states.append(self.tail[m][0])
+                    uvs.append(self.tail[m][1])
+                    continue
                 nxt = s.empty_state()
                 if w:
                     uvs.append(s.empty_velocity())
                     self._step_with_velocity(states[-1], nxt, uvs[-1])
                 else:
+                    uvs.append(None)
                     s.step(states[-1], nxt, 1, self.tau)
                 states.append(nxt)
             for n in range(stop - 1, start - 1, -1):

@@ -140,16 +140,20 @@ __device__ inline void root_bar(T s, T A, T B, T sbar, T &Ab, T &Bb, T &Cb)
     Cb = q;
 }
 
-// Occupancy floor of the adjoint step.  The adjoint is ALU-bound (about
-// twice its memory time); the Q values of x and of lambda, the equilibrium
-// tables and the adjoints of the sums need 170-190 VGPRs in single
-// precision, so two waves per SIMD run without scratch.  At three waves
-// (168 VGPRs) the forced alpha_Higher adjoint fits with 8 bytes of scratch
-// but measured 294 us against 207 us at two (128^3).
+// Occupancy floor of the adjoint step.  The adjoint is ALU-bound (its VALU
+// issue exceeds its memory time), and a third wave per SIMD hides more of its
+// memory latency.  In single precision the Q values of x and of lambda, the
+// equilibrium tables and the adjoints of the sums fit 168 VGPRs in the
+// alpha_Higher and BGK kernels, the forced alpha_Higher kernel with four
+// registers spilled once per lane (128^3 forced: 182 us per launch against
+// 190 us at two waves, on one box).  Parking x in LDS instead (27 KiB per
+// block, 147 VGPRs, no scratch) measured 190 us.  The D3Q27 alpha_Lower
+// kernel spills 42 registers at three waves and the double-precision kernels
+// several hundred bytes per lane; they run at two.
 template <typename S, int MODE>
 constexpr int adj_waves()
 {
-    return 2;
+    return (std::is_same<typename Storage<S>::T, double>::value || MODE == MODE_LOWER) ? 2 : 3;
 }
 
 // Adjoint (vector-Jacobian product) of one step at one cell.
@@ -229,7 +233,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
     }
     // the force gradient accumulated so far, read at the start for the same
     // reason (its read-modify-write is each lane's own cell); without a
-    // gradient buffer the force itself (same size) is read and discarded
+    // gradient buffer the force itself (same size) is read and discarded.
+    // Read at the end instead, its latency is exposed: 190 against 182 us
+    // per launch at 128^3, though its three registers then cause no spill.
     float fg0[3] = {0.f, 0.f, 0.f};
     if (FORCE) {
         const float *fp = a.force_grad ? a.force_grad : a.force;
@@ -798,7 +804,7 @@ static long long stencil_blocks(const Grid &g)
 hipError_t free_loss_scratch(LossScratch &sc)
 {
     hipError_t e = hipSuccess, r;
-    void *bufs[4] = {sc.u, sc.rho, sc.vort, sc.part};
+    void *bufs[3] = {sc.u, sc.rho, sc.part};
     for (void *b : bufs) {
         if (!b) continue;
         r = hipFree(b);
@@ -817,7 +823,6 @@ static hipError_t ensure_scratch(LossScratch &sc, const Grid &g)
     hipError_t e = free_loss_scratch(sc);
     if (e == hipSuccess) e = hipMalloc((void **)&sc.u, sizeof(float) * 3 * g.N);
     if (e == hipSuccess) e = hipMalloc((void **)&sc.rho, sizeof(float) * g.N);
-    if (e == hipSuccess) e = hipMalloc((void **)&sc.vort, sizeof(float) * 3 * g.N);
     if (e == hipSuccess) e = hipMalloc((void **)&sc.part, sizeof(double) * parts);
     if (e != hipSuccess) {
         // the allocation error is the one reported; the release of what was
@@ -900,9 +905,10 @@ hipError_t launch_kinetic_loss_noalloc(double *parts, int dtype, const Grid &g, 
 
 // ---------------------------------------------------------------------------
 // Dissipation loss L = weight * sum |omega|^2, omega from periodic central
-// differences of u = (j + F/2) / rho.  Three passes: velocity and density
-// (reads the state once), vorticity (+ loss), then the seed from u, rho and
-// the vorticity.
+// differences of u = (j + F/2) / rho.  The velocity and density come from a
+// pass over the state or from the field a step wrote; the loss value and the
+// seed are then one stencil pass each over that field, the seed forming the
+// vorticity it needs at the neighbours on the fly (no vorticity array).
 // ---------------------------------------------------------------------------
 template <int D, typename S>
 __global__ __launch_bounds__(256) void k_velocity(Grid g, const S *__restrict__ f, const float *__restrict__ force,
@@ -930,88 +936,121 @@ __global__ __launch_bounds__(256) void k_velocity(Grid g, const S *__restrict__ 
     }
 }
 
-// Row offsets of a cell's six face neighbours on the periodic grid, for the
-// (x-block, y, z) launch: x -+ 1 as lane indices, y -+ 1 and z -+ 1 as row
-// starts (element offsets within one field).
-struct Nbr {
-    int x, xp, xm;
-    long long row, ryp, rym, rzp, rzm;
-    __device__ Nbr(const Grid &g)
+// Periodic neighbourhood of a lane's cell, for the (x-block, y, z) launch:
+// the cell at (dx, dy, dz) from it, |dx|, |dy|, |dz| <= 2, on any grid
+// (extents 1 and 2 included), addressed as a block-uniform row start plus
+// the lane's 32-bit x.
+struct Stencil {
+    unsigned xs[5];        // x of the offsets -2..2
+    long long rows[5][5];  // [dz + 2][dy + 2]: element offset of the row start
+    bool in;
+    __device__ Stencil(const Grid &g)
     {
         const int nx = g.nx, ny = g.ny, nz = g.nz;
+        const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+        in = x < nx;
         const int y = (int)blockIdx.y, z = (int)blockIdx.z;
-        x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-        xp = x + 1 == nx ? 0 : x + 1;
-        xm = x == 0 ? nx - 1 : x - 1;
-        const int yp = y + 1 == ny ? 0 : y + 1, ym = y == 0 ? ny - 1 : y - 1;
-        const int zp = z + 1 == nz ? 0 : z + 1, zm = z == 0 ? nz - 1 : z - 1;
-        row = ((long long)z * ny + y) * nx;
-        ryp = ((long long)z * ny + yp) * nx;
-        rym = ((long long)z * ny + ym) * nx;
-        rzp = ((long long)zp * ny + y) * nx;
-        rzm = ((long long)zm * ny + y) * nx;
+        // v in [c - 2, c + 2] with c in [0, n): n is added or subtracted at
+        // most twice (twice only when n is 1 or 2)
+        auto wrap = [](int v, int n) {
+            if (v < 0) v += n;
+            if (v < 0) v += n;
+            if (v >= n) v -= n;
+            if (v >= n) v -= n;
+            return v;
+        };
+        int ys[5], zs[5];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            xs[o] = (unsigned)wrap(x + o - 2, nx);
+            ys[o] = wrap(y + o - 2, ny);
+            zs[o] = wrap(z + o - 2, nz);
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) rows[a][b] = ((long long)zs[a] * ny + ys[b]) * nx;
     }
-    // value of field v at the neighbour along axis a, direction dir (+-1)
-    __device__ double at(const float *v, int a, int dir) const
+    // the value of a field (its start: f) at the offset
+    __device__ float at(const float *__restrict__ f, int dx, int dy, int dz) const
     {
-        if (a == 0) return (double)v[row + (dir > 0 ? xp : xm)];
-        if (a == 1) return (double)v[(dir > 0 ? ryp : rym) + x];
-        return (double)v[(dir > 0 ? rzp : rzm) + x];
+        return *lane_ptr(f + rows[dz + 2][dy + 2], xs[dx + 2]);
     }
+    __device__ long long cell() const { return rows[2][2] + xs[2]; }
 };
 
 // vorticity component k = (a, b): omega_k = d_a u_b - d_b u_a
-__device__ inline void vort_axes(int D, int k, int &a, int &b)
+__device__ constexpr int vort_a(int D, int k) { return D == 2 ? 0 : (k == 0 ? 1 : (k == 1 ? 2 : 0)); }
+__device__ constexpr int vort_b(int D, int k) { return D == 2 ? 1 : (k == 0 ? 2 : (k == 1 ? 0 : 1)); }
+
+// omega_k at the cell offset o = (ox, oy, oz) from the lane's cell
+template <int D, int K>
+__device__ inline double omega_at(const float *__restrict__ u, long long N, const Stencil &s, int ox, int oy, int oz)
 {
-    if (D == 2) { a = 0; b = 1; return; }
-    if (k == 0) { a = 1; b = 2; }
-    else if (k == 1) { a = 2; b = 0; }
-    else { a = 0; b = 1; }
+    constexpr int a = vort_a(D, K), b = vort_b(D, K);
+    const int o[3] = {ox, oy, oz};
+    int p[3] = {o[0], o[1], o[2]}, m[3] = {o[0], o[1], o[2]};
+    p[a] += 1;
+    m[a] -= 1;
+    const double dub = 0.5 * ((double)s.at(u + b * N, p[0], p[1], p[2]) - (double)s.at(u + b * N, m[0], m[1], m[2]));
+    int q[3] = {o[0], o[1], o[2]}, r[3] = {o[0], o[1], o[2]};
+    q[b] += 1;
+    r[b] -= 1;
+    const double dua = 0.5 * ((double)s.at(u + a * N, q[0], q[1], q[2]) - (double)s.at(u + a * N, r[0], r[1], r[2]));
+    return dub - dua;
 }
 
+// The loss alone: weight * sum_x |omega(x)|^2, one partial sum per block.
+// (Forming the total in the same launch, the last block to finish adding the
+// partials after a counter of finished blocks, measured 20 times slower: the
+// device-scope release fence of every block writes back the L2.)
 template <int D>
-__global__ __launch_bounds__(256) void k_vorticity(Grid g, const float *__restrict__ u, float *__restrict__ vort,
-                                                   double *part, double weight)
+__global__ __launch_bounds__(256) void k_diss_loss(Grid g, const float *__restrict__ u, double *part, double weight)
 {
-    const Nbr n(g);
+    const Stencil s(g);
     const long long N = g.N;
     double e = 0.0;
-    if (n.x < g.nx) {
-        constexpr int nv = D == 2 ? 1 : 3;
-#pragma unroll
-        for (int k = 0; k < nv; ++k) {
-            int a, b;
-            vort_axes(D, k, a, b);
-            const double dub = 0.5 * (n.at(u + b * N, a, 1) - n.at(u + b * N, a, -1));
-            const double dua = 0.5 * (n.at(u + a * N, b, 1) - n.at(u + a * N, b, -1));
-            const double om = dub - dua;
-            vort[k * N + n.row + n.x] = (float)om;
-            e += om * om;
+    if (s.in) {
+        const double o0 = omega_at<D, 0>(u, N, s, 0, 0, 0);
+        e = o0 * o0;
+        if (D == 3) {
+            const double o1 = omega_at<D, 1>(u, N, s, 0, 0, 0), o2 = omega_at<D, 2>(u, N, s, 0, 0, 0);
+            e += o1 * o1 + o2 * o2;
         }
         e *= weight;
     }
-    if (part) block_partial(e, part, ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+    block_partial(e, part, ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
+}
+
+// ubar = dL/du(x): L = w sum_y omega^2 with omega_k(y) containing
+// (u_b(y + e_a) - u_b(y - e_a))/2 - (u_a(y + e_b) - u_a(y - e_b))/2, so
+// ubar_b += w (omega_k(x - e_a) - omega_k(x + e_a)) and
+// ubar_a -= w (omega_k(x - e_b) - omega_k(x + e_b)).
+template <int D, int K>
+__device__ inline void ubar_add(const float *__restrict__ u, long long N, const Stencil &s, double w, double (&ub)[3])
+{
+    constexpr int a = vort_a(D, K), b = vort_b(D, K);
+    int e[3] = {0, 0, 0};
+    e[a] = 1;
+    ub[b] += w * (omega_at<D, K>(u, N, s, -e[0], -e[1], -e[2]) - omega_at<D, K>(u, N, s, e[0], e[1], e[2]));
+    int f[3] = {0, 0, 0};
+    f[b] = 1;
+    ub[a] -= w * (omega_at<D, K>(u, N, s, -f[0], -f[1], -f[2]) - omega_at<D, K>(u, N, s, f[0], f[1], f[2]));
 }
 
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restrict__ u, const float *__restrict__ rho,
-                                                   const float *__restrict__ vort, T *lam, T *seed, double weight,
-                                                   float *force_grad)
+                                                   T *lam, T *seed, double weight, float *force_grad)
 {
     constexpr int Q = Lat<D>::Q;
-    const Nbr n(g);
-    if (n.x >= g.nx) return;
-    const long long N = g.N, cell = n.row + n.x;
-    // ubar = dL/du(x): L = w sum omega^2 with omega_k(y) containing
-    // (u_b(y + e_a) - u_b(y - e_a))/2 - (u_a(y + e_b) - u_a(y - e_b))/2
+    const Stencil s(g);
+    if (!s.in) return;
+    const long long N = g.N, cell = s.cell();
     double ub[3] = {0, 0, 0};
-    constexpr int nv = D == 2 ? 1 : 3;
-#pragma unroll
-    for (int k = 0; k < nv; ++k) {
-        int a, b;
-        vort_axes(D, k, a, b);
-        ub[b] += weight * (n.at(vort + k * N, a, -1) - n.at(vort + k * N, a, 1));
-        ub[a] -= weight * (n.at(vort + k * N, b, -1) - n.at(vort + k * N, b, 1));
+    ubar_add<D, 0>(u, N, s, weight, ub);
+    if (D == 3) {
+        ubar_add<D, 1>(u, N, s, weight, ub);
+        ubar_add<D, 2>(u, N, s, weight, ub);
     }
     const double ir = 1.0 / (double)rho[cell];
     double uc[3] = {0, 0, 0};
@@ -1019,27 +1058,24 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restri
     for (int c = 0; c < D; ++c) uc[c] = (double)u[c * N + cell];
     // du_c/df_i = (c_ic - u_c) / rho: dL/df_i = s0 + c_i . s with
     // s0 = -ubar . u / rho and s = ubar / rho
-    if (seed) {
-        double ubu = 0.0;
+    double ubu = 0.0;
 #pragma unroll
-        for (int c = 0; c < D; ++c) ubu += ub[c] * uc[c];
+    for (int c = 0; c < D; ++c) ubu += ub[c] * uc[c];
+    if (seed) {
         seed[cell] = (T)(-ubu * ir);
 #pragma unroll
         for (int c = 0; c < D; ++c) seed[(long long)(1 + c) * N + cell] = (T)(ub[c] * ir);
     }
     if (lam) {
-        double ubu = 0.0;
-#pragma unroll
-        for (int c = 0; c < D; ++c) ubu += ub[c] * uc[c];
 #pragma unroll
         for (int i = 0; i < Q; ++i) {
-            double s = -ubu;
+            double sv = -ubu;
 #pragma unroll
             for (int c = 0; c < D; ++c) {
-                if (Lat<D>::c(i, c) > 0) s += ub[c];
-                if (Lat<D>::c(i, c) < 0) s -= ub[c];
+                if (Lat<D>::c(i, c) > 0) sv += ub[c];
+                if (Lat<D>::c(i, c) < 0) sv -= ub[c];
             }
-            lam[(long long)i * N + cell] += (T)(s * ir);
+            lam[(long long)i * N + cell] += (T)(sv * ir);
         }
     }
     // du_c/dF_c = 1 / (2 rho) through the half-force shift
@@ -1078,17 +1114,17 @@ static hipError_t launch_diss_d(LossScratch &sc, int dtype, const Grid &g, const
     }
     const int bx = block_x(g.nx);
     const dim3 sgrid((unsigned)((g.nx + bx - 1) / bx), (unsigned)g.ny, (unsigned)g.nz), sblock(bx);
-    double *part = loss ? sc.part : nullptr;
-    hipLaunchKernelGGL((k_vorticity<D>), sgrid, sblock, 0, s, g, u, sc.vort, part, weight);
-    if (loss)
-        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (const double *)part, stencil_blocks(g), loss);
+    if (loss) {
+        hipLaunchKernelGGL((k_diss_loss<D>), sgrid, sblock, 0, s, g, u, sc.part, weight);
+        hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(1024), 0, s, (const double *)sc.part, stencil_blocks(g), loss);
+    }
     if (lam || seed || force_grad) {
         if (dtype == 0)
-            hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, u, rho,
-                               sc.vort, (double *)lam, (double *)seed, weight, force_grad);
+            hipLaunchKernelGGL((k_diss_seed<D, double>), sgrid, sblock, 0, s, g, u, rho, (double *)lam,
+                               (double *)seed, weight, force_grad);
         else
-            hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, u, rho,
-                               sc.vort, (float *)lam, (float *)seed, weight, force_grad);
+            hipLaunchKernelGGL((k_diss_seed<D, float>), sgrid, sblock, 0, s, g, u, rho, (float *)lam,
+                               (float *)seed, weight, force_grad);
     }
     return hipGetLastError();
 }

@@ -67,12 +67,10 @@ struct AdjArgs {
 };
 hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s);
 // Scratch of the losses, owned by a handle (so by its device) and grown on
-// demand: velocity and density of the state, vorticity, and one partial sum
-// per block.
+// demand: velocity and density of the state, and one partial sum per block.
 struct LossScratch {
     float *u = nullptr;      // [D][N], u = (j + F/2) / rho
     float *rho = nullptr;    // [N]
-    float *vort = nullptr;   // [nv][N], nv = 1 (2-D) or 3 (3-D)
     double *part = nullptr;  // one partial sum per block
     long long cells = 0, parts = 0;
 };

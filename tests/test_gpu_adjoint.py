@@ -278,6 +278,52 @@ def test_kinetic_and_dissipation_seeds(es):
         assert np.max(np.abs(lam.double().cpu().numpy() - f.grad.numpy())) <= 1e-5 * np.max(np.abs(f.grad.numpy()))
 
 
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+@pytest.mark.parametrize("D,shape", [(2, (1, 5)), (2, (2, 9)), (2, (13, 70)), (3, (1, 1, 5)), (3, (2, 2, 9)),
+                                     (3, (5, 1, 7)), (3, (3, 4, 257))])
+def test_dissipation_seed_stencil_grids(es, D, shape, dtype):
+    """The dissipation loss, its full seed, its compact seed and the direct
+    force gradient on grids with extents of 1 and 2 (the periodic stencil's
+    wrap-around folds onto the cell itself), small odd extents and rows of
+    two blocks and a ragged tail, against autograd of the FP64 reference."""
+    f0 = _state(D, shape, 21, 1e-3)
+    F = W.random_force(shape, D, amplitude=1e-3, seed=22)
+    s = es.Solver("D2Q9" if D == 2 else "D3Q27", shape, dtype=dtype)
+    Ft = None
+    if dtype == "f32":
+        s.set_force(_t(F).float().cuda())
+        Ft = _t(F).float().double().requires_grad_(True)
+    fd = _t(f0).to(s.storage_dtype).cuda()
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    full = s.empty_adjoint().zero_()
+    fg = torch.zeros((D,) + shape, dtype=torch.float32, device="cuda") if Ft is not None else None
+    s.dissipation_loss(fd, loss=loss, lam=full, weight=0.3, force_grad=fg)
+    seed = s.empty_seed()
+    fg_c = torch.zeros_like(fg) if fg is not None else None
+    s.dissipation_seed(fd, seed, weight=0.3, force_grad=fg_c)
+    f = _t(fd.double().cpu().numpy()).requires_grad_(True)
+    L = TR.dissipation(f, 0.3, Ft)
+    L.backward()
+    # the velocity field the loss reads is single precision in every storage
+    # type (as in test_kinetic_and_dissipation_seeds)
+    tol = 1e-5
+    ref = f.grad.numpy()
+    scale = np.max(np.abs(ref))
+    c, _ = oracle.lattice(D)
+    sd = seed.double().cpu().numpy()
+    expanded = sd[0][None] + np.tensordot(c[:, :D].astype(float), sd[1:], axes=(1, 0))
+    e_loss = abs(loss.item() - L.item()) / abs(L.item())
+    e_full = np.max(np.abs(full.double().cpu().numpy() - ref)) / scale
+    e_comp = np.max(np.abs(expanded - ref)) / scale
+    _log(f"[diss stencil D{D} {shape} {dtype}] loss {e_loss:.2e} full {e_full:.2e} compact {e_comp:.2e}")
+    assert e_loss <= tol and e_full <= tol and e_comp <= tol
+    if Ft is not None:
+        gF = Ft.grad.numpy()
+        e_f = np.max(np.abs(fg.double().cpu().numpy() - gF)) / np.max(np.abs(gF))
+        assert e_f <= tol, e_f
+        assert torch.equal(fg, fg_c)
+
+
 def _ke_np(f):
     r, v = oracle.moments(f)
     return 0.5 * np.sum(r * (v ** 2).sum(0))
