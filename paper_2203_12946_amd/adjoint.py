@@ -145,6 +145,12 @@ class Rollout:
                     uvs.append(None)
                     s.step(states[-1], nxt, 1, self.tau)
                 states.append(nxt)
+            if kept:
+                # the kept states now live in this segment's list only, so
+                # they are freed with it: the backward's memory peak stays at
+                # one segment of states (a later backward of the same forward
+                # recomputes them)
+                self.tail = {}
             for n in range(stop - 1, start - 1, -1):
                 f_n = states[n - start]
                 s.adjoint_step(f_n, lam, other, self.tau, force_grad=force_grad, seed_next=pending)
@@ -156,6 +162,7 @@ class Rollout:
                     else:
                         s.dissipation_seed(f_n, seed, weight=w, force_grad=force_grad)
                     pending = seed
+            del states, uvs
             n_end = start
         return lam
 

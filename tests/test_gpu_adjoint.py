@@ -399,6 +399,39 @@ def test_rollout_force_gradient_vs_oracle_fd(es):
     assert worst < 1e-4
 
 
+def test_rollout_schedules_agree(es):
+    """The checkpoint schedule does not change the gradient: a forced 3-D
+    rollout with the dissipation loss over 7 steps, checkpointed every 1, 4
+    and 20 steps (every state a checkpoint; a last segment of three states,
+    two of them kept by the forward; one segment that the forward keeps
+    whole), gives the same bits, and so does a second backward of one forward
+    (it recomputes the states the first one used and released)."""
+    from paper_2203_12946_amd.adjoint import Rollout
+    shape = (5, 6, 70)
+    n = 7
+    rho, u = W.taylor_green_3d(0, shape=shape, u0=0.08, noise=1e-3, seed=31)
+    F = torch.from_numpy(W.random_force(shape, 3, amplitude=1e-5, seed=32)).float().cuda()
+    tau = 2e-3
+    s = es.Solver("D3Q27", shape, dtype="f32")
+    s.set_force(F)
+    f0 = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
+    results = []
+    for ckpt in (1, 4, 20):
+        ro = Rollout(s, tau, n, ckpt, diss_weight=1e-3)
+        loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+        fN = ro.forward(f0, loss)
+        for rep in range(2 if ckpt == 4 else 1):
+            fg = torch.zeros_like(F)
+            lam0 = ro.backward(fN * 0.5, diss_grad=1.0, force_grad=fg)
+            results.append((f"ckpt {ckpt} backward {rep}", loss.item(), lam0.clone(), fg))
+    ref = results[0]
+    for name, L, lam0, fg in results[1:]:
+        _log(f"[rollout schedules] {name}: loss {L:.15e}")
+        assert L == ref[1], name
+        assert torch.equal(lam0, ref[2]), name
+        assert torch.equal(fg, ref[3]), name
+
+
 def test_dot_product_identity(es):
     """<J^T lam, v> = <lam, J v> for one FP64 step, J v by central differences
     of the GPU forward step."""
