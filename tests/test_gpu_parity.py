@@ -494,3 +494,44 @@ def test_degenerate_and_ragged_grids(es, shape):
     s2.step(torch.from_numpy(f2.copy()).cuda(), b2, 4, 3e-3)
     torch.cuda.synchronize()
     assert float(np.max(np.abs(b2.cpu().numpy() - ref2))) < 1e-13
+
+
+@pytest.mark.parametrize("dtype", ["f64", "f32", "f16s"])
+def test_runs_are_bitwise_reproducible(es, dtype):
+    """Two runs of the same steps from the same state give the same bits:
+    the state path has no atomics and no order-dependent reductions (the
+    FP64 diagnostics are summed with atomics, so only their counts are
+    compared exactly), and so does the adjoint step."""
+    from tests._states import three_regime_state
+    shape = (3, 5, 300)
+    f0 = three_regime_state(3, shape, 41)
+    tau = 3e-3
+    runs = []
+    for _ in range(2):
+        s = es.Solver("D3Q27", shape, dtype=dtype)
+        a = torch.from_numpy(f0).to(s.storage_dtype).cuda() if dtype != "f16s" else None
+        if a is None:
+            # shifted storage holds f - w
+            c, w = oracle.lattice(3)
+            a = torch.from_numpy(f0 - w.reshape(27, 1, 1, 1)).to(s.storage_dtype).cuda()
+        alpha = torch.empty(shape, dtype=s.compute_dtype, device="cuda")
+        s.set_alpha_field(alpha)
+        s.set_stats(True)
+        b = s.empty_state()
+        s.step(a, b, 7, tau)
+        st = s.stats()
+        runs.append((b.clone(), alpha.clone(), st))
+        if dtype != "f16s":
+            lam = torch.from_numpy(np.random.default_rng(5).standard_normal(f0.shape)).to(s.compute_dtype).cuda()
+            out = s.empty_adjoint()
+            s.adjoint_step(a, lam, out, tau)
+            runs[-1] = runs[-1] + (out.clone(),)
+    (b1, a1, s1, *r1), (b2, a2, s2, *r2) = runs
+    assert torch.equal(b1, b2)
+    assert torch.equal(torch.nan_to_num(a1, nan=-1.0), torch.nan_to_num(a2, nan=-1.0))
+    for k in ("n_cells", "n_gated", "n_guard", "n_nonpos", "n_exact"):
+        assert s1[k] == s2[k], k
+    assert s1["alpha_min"] == s2["alpha_min"] and s1["alpha_max"] == s2["alpha_max"]
+    assert abs(s1["mass"] - s2["mass"]) <= 1e-13 * abs(s1["mass"])
+    if r1:
+        assert torch.equal(r1[0], r2[0])
