@@ -335,8 +335,41 @@ def time_adjoint_2d(es, torch, W):
     fwd = sorted(r[0] for r in runs)[2]
     bwd = sorted(r[1] for r in runs)[2]
     L, g = runs[-1][2], runs[-1][3]
+
+    # The same gradient with the rollout's two sweeps replayed from HIP graphs
+    # (the equilibrium, the loss and its seed, and the equilibrium's adjoint
+    # stay eager launches): the launch-bound size is where graphs pay.
+    u0 = torch.from_numpy(u).cuda()
+    f0 = s.init_equilibrium(r, u0)
+    gr = A.GraphedRollout(s, f0, wl.tau, wl.steps, 20)
+    loss = torch.zeros(1, dtype=torch.float64, device="cuda")
+
+    def run_graphed():
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.init_equilibrium(r, u0, out=gr.f0)
+        fN, _ = gr.forward()
+        loss.zero_()
+        s.kinetic_loss(fN, loss=loss)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.kinetic_loss(fN, lam=gr.lam_final, scale=1.0)
+        lam0, _ = gr.backward()
+        gu = s.equilibrium_vjp(r, u0, lam0)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        return t1 - t0, t2 - t1, gu
+
+    run_graphed()
+    gruns = [run_graphed() for _ in range(5)]
+    gfwd = sorted(x[0] for x in gruns)[2]
+    gbwd = sorted(x[1] for x in gruns)[2]
+    graphed = dict(forward_s=gfwd, backward_s=gbwd, ratio=gbwd / gfwd, timing="median of 5",
+                   grad_equal_eager=bool(torch.equal(gruns[-1][2], g)),
+                   loss_equal_eager=bool(loss.item() == L))
     return dict(workload=wl.name, steps=wl.steps, ckpt_every=20, forward_s=fwd, backward_s=bwd,
-                ratio=bwd / fwd, loss=L, grad_finite=bool(torch.isfinite(g).all().item()), timing="median of 5")
+                ratio=bwd / fwd, loss=L, grad_finite=bool(torch.isfinite(g).all().item()), timing="median of 5",
+                hip_graphs=graphed)
 
 
 def cpu_baseline(W, wl, seconds_target: float = 10.0):
@@ -560,7 +593,9 @@ def main():
         _log(f"bench: adjoint/forward = {adj['ratio']:.2f}")
         _log("bench: adjoint 256^2")
         adj["d2q9_adjoint_256"] = time_adjoint_2d(es, torch, W)
-        _log(f"bench: 2-D adjoint/forward = {adj['d2q9_adjoint_256']['ratio']:.2f}")
+        a2 = adj["d2q9_adjoint_256"]
+        _log(f"bench: 2-D adjoint/forward = {a2['ratio']:.2f} (HIP graphs: forward {a2['hip_graphs']['forward_s'] * 1e3:.2f} ms, "
+             f"backward {a2['hip_graphs']['backward_s'] * 1e3:.2f} ms)")
 
     cpu = None
     if not args.no_cpu:

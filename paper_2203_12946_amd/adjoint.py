@@ -20,6 +20,9 @@ schedules them:
   adjoint step that reads it.  The adjoint kernel also accumulates the
   body-force gradient.
 
+``GraphedRollout`` captures a rollout's forward and backward sweeps in two
+HIP graphs for grids small enough that launches dominate.
+
 Autograd functions wrap the three pieces of a training objective:
 ``equilibrium`` (initial state from rho, u; gradient w.r.t. u), ``rollout``
 (state after n steps and the accumulated dissipation; gradients w.r.t. the
@@ -174,6 +177,79 @@ class Rollout:
             self.s.step(cur, nxt, 1, self.tau)
             cur, nxt = nxt, cur
         return cur
+
+
+class GraphedRollout:
+    """A rollout captured in two HIP graphs, for grids where the kernel
+    launches rather than the kernels set the time (a small 2-D lattice steps
+    in a few microseconds).
+
+    The forward graph runs ``Rollout.forward`` from the static state ``f0``
+    (copy an initial state into it before each replay) and leaves the final
+    state in ``fN`` and, with a dissipation weight, the accumulated loss in
+    ``loss``.  The backward graph runs ``Rollout.backward`` from the static
+    adjoint ``lam_final`` with the loss gradient ``diss_grad`` fixed at
+    capture, and leaves the adjoint of ``f0`` in ``lam0`` and, with
+    ``with_force_grad``, the gradient with respect to the solver's
+    registered force in ``force_grad``.  A backward replay uses the states of
+    the last forward replay.
+
+    A replay relaunches the captured kernels on the same buffers: its results
+    equal an eager rollout's bit for bit.  The solver's settings at capture
+    (mode, force, walls) are part of the graphs.  Construction runs the
+    rollout once eagerly (the first allocations of the caching allocator and
+    of the library's loss scratch, which a capture may not make) and then
+    captures; the library's calls in a rollout launch kernels and device
+    copies only (no memset, no allocation, no synchronisation).
+    """
+
+    def __init__(self, solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
+                 diss_weight: float | None = None, diss_grad: float = 1.0, with_force_grad: bool = False):
+        s = solver
+        self.ro = Rollout(s, tau, nsteps, ckpt_every, diss_weight)
+        self.f0 = f0.detach().clone()
+        self.lam_final = s.empty_adjoint().zero_()
+        self.loss = torch.zeros(1, dtype=torch.float64, device=s.device)
+        self.force_grad = (torch.zeros((s.D,) + s.shape, dtype=torch.float32, device=s.device)
+                           if with_force_grad else None)
+        with_loss = diss_weight is not None
+
+        def fwd():
+            self.loss.zero_()
+            return self.ro.forward(self.f0, self.loss if with_loss else None)
+
+        def bwd():
+            if self.force_grad is not None:
+                self.force_grad.zero_()
+            return self.ro.backward(self.lam_final, diss_grad=diss_grad, force_grad=self.force_grad)
+
+        cur = torch.cuda.current_stream(s.device)
+        side = torch.cuda.Stream(device=s.device)
+        side.wait_stream(cur)
+        with torch.cuda.stream(side):
+            fwd()
+            bwd()
+        cur.wait_stream(side)
+        torch.cuda.synchronize(s.device)
+        self._gf = torch.cuda.CUDAGraph()
+        self._gb = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(self._gf):
+            self.fN = fwd()
+        # every state the backward graph reads, held here whatever the
+        # backward sweep does with its own references
+        self._reads = (dict(self.ro.ckpts), dict(self.ro.ckpt_uv), dict(self.ro.tail), self.ro.uv_end)
+        with torch.cuda.graph(self._gb):
+            self.lam0 = bwd()
+
+    def forward(self):
+        """Replays the forward graph: (fN, loss)."""
+        self._gf.replay()
+        return self.fN, self.loss
+
+    def backward(self):
+        """Replays the backward graph: (lam0, force_grad)."""
+        self._gb.replay()
+        return self.lam0, self.force_grad
 
 
 class _Equilibrium(torch.autograd.Function):
