@@ -602,19 +602,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
     if (DIAG && a.stats) block_reduce_stats(ls, a.stats + (blockIdx.y + blockIdx.z) % kStatSlots);
 }
 
-// Occupancy cap of the alpha = 2 steps in the 4- and 2-byte formats.  With
-// their fewer registers the hardware would run five waves per SIMD (F32:
+// Occupancy cap of the D3Q27 alpha = 2 steps in the 4- and 2-byte formats.
+// With their fewer registers the hardware would run five waves per SIMD (F32:
 // 94 VGPRs), which measured slower than four at 256^3 (F32 0.635 -> 0.627 ms,
 // F16-shifted 0.337 -> 0.324 ms; the closed-form steps run at four already):
-// past four waves the added concurrent streams cost the HBM more than they
-// hide.  Dynamic LDS that the kernel never touches bounds the blocks per CU.
-// Four waves per SIMD are 16 per CU, so a block of w waves gets a
-// 16 / w share of the CU's 160 KiB, less 1 KiB for the kernel's own static
-// LDS (the statistics reduction's 544 bytes).
-template <typename S, int MODE>
+// past four waves the added concurrent streams (27 per wave) cost the HBM
+// more than they hide.  D2Q9, with 9 streams per wave, keeps the hardware's
+// occupancy.  Dynamic LDS that the kernel never touches bounds the blocks per
+// CU.  Four waves per SIMD are 16 per CU, so a block of w waves gets a 16 / w
+// share of the CU's 160 KiB, less 1 KiB for the kernel's own static LDS (the
+// statistics reduction's 544 bytes).
+template <int D, typename S, int MODE>
 static unsigned occupancy_cap_lds(int bx)
 {
-    if constexpr ((MODE == MODE_BGK || MODE == MODE_LBGK) && !std::is_same<typename Storage<S>::T, double>::value) {
+    if constexpr (D == 3 && (MODE == MODE_BGK || MODE == MODE_LBGK) &&
+                  !std::is_same<typename Storage<S>::T, double>::value) {
         const int blocks = 16 / (bx / 64);  // bx is 64, 128, 192 or 256
         return (unsigned)((160 * 1024 / blocks - 1024) & ~511);
     }
@@ -678,7 +680,7 @@ static hipError_t launch_step_t(bool diag, const StepArgs &a, hipStream_t s)
         }
         return hipErrorInvalidValue;
     }
-    const unsigned lds = occupancy_cap_lds<S, MODE>(bx);
+    const unsigned lds = occupancy_cap_lds<D, S, MODE>(bx);
     if (diag) hipLaunchKernelGGL((k_step<D, S, MODE, true, false>), grid, block, lds, s, a);
     else hipLaunchKernelGGL((k_step<D, S, MODE, false, false>), grid, block, lds, s, a);
     return hipGetLastError();
