@@ -1022,20 +1022,39 @@ __global__ __launch_bounds__(256) void k_diss_loss(Grid g, const float *__restri
     block_partial(e, part, ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
-// ubar = dL/du(x): L = w sum_y omega^2 with omega_k(y) containing
-// (u_b(y + e_a) - u_b(y - e_a))/2 - (u_a(y + e_b) - u_a(y - e_b))/2, so
-// ubar_b += w (omega_k(x - e_a) - omega_k(x + e_a)) and
-// ubar_a -= w (omega_k(x - e_b) - omega_k(x + e_b)).
-template <int D, int K>
-__device__ inline void ubar_add(const float *__restrict__ u, long long N, const Stencil &s, double w, double (&ub)[3])
+// ubar = dL/du(x) for L = w sum_y |curl u(y)|^2, curl taken with the
+// periodic central difference D_a f(y) = (f(y + e_a) - f(y - e_a)) / 2.  D_a
+// is antisymmetric and the D_a commute, so curl is self-adjoint and
+//   ubar = 2 w curl curl u = 2 w (grad div u - sum_a D_a D_a u),
+//   ubar_c = (w / 2) sum_{a != c} [u_a(x + e_c + e_a) - u_a(x + e_c - e_a)
+//            - u_a(x - e_c + e_a) + u_a(x - e_c - e_a)
+//            - u_c(x + 2 e_a) + 2 u_c(x) - u_c(x - 2 e_a)]
+// (the a = c terms of the two operators cancel): 6 D - 5 loads per
+// component instead of the vorticity at four neighbours per term.
+template <int D>
+__device__ inline double ubar_c(const float *__restrict__ u, long long N, const Stencil &s, int c)
 {
-    constexpr int a = vort_a(D, K), b = vort_b(D, K);
-    int e[3] = {0, 0, 0};
-    e[a] = 1;
-    ub[b] += w * (omega_at<D, K>(u, N, s, -e[0], -e[1], -e[2]) - omega_at<D, K>(u, N, s, e[0], e[1], e[2]));
-    int f[3] = {0, 0, 0};
-    f[b] = 1;
-    ub[a] -= w * (omega_at<D, K>(u, N, s, -f[0], -f[1], -f[2]) - omega_at<D, K>(u, N, s, f[0], f[1], f[2]));
+    const float *uc = u + (long long)c * N;
+    const double u0 = (double)s.at(uc, 0, 0, 0);
+    double t = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (a == c) continue;
+        const float *ua = u + (long long)a * N;
+        int p[3] = {0, 0, 0}, m[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+        p[c] = 1;
+        m[c] = -1;
+        const int pa[3] = {p[0] + (a == 0), p[1] + (a == 1), p[2] + (a == 2)};
+        const int pb[3] = {p[0] - (a == 0), p[1] - (a == 1), p[2] - (a == 2)};
+        const int ma[3] = {m[0] + (a == 0), m[1] + (a == 1), m[2] + (a == 2)};
+        const int mb[3] = {m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2)};
+        e2[a] = 2;
+        const double cross = ((double)s.at(ua, pa[0], pa[1], pa[2]) - (double)s.at(ua, pb[0], pb[1], pb[2])) -
+                             ((double)s.at(ua, ma[0], ma[1], ma[2]) - (double)s.at(ua, mb[0], mb[1], mb[2]));
+        const double lap = ((double)s.at(uc, e2[0], e2[1], e2[2]) - u0) + ((double)s.at(uc, -e2[0], -e2[1], -e2[2]) - u0);
+        t += cross - lap;
+    }
+    return t;
 }
 
 template <int D, typename T>
@@ -1047,11 +1066,8 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restri
     if (!s.in) return;
     const long long N = g.N, cell = s.cell();
     double ub[3] = {0, 0, 0};
-    ubar_add<D, 0>(u, N, s, weight, ub);
-    if (D == 3) {
-        ubar_add<D, 1>(u, N, s, weight, ub);
-        ubar_add<D, 2>(u, N, s, weight, ub);
-    }
+#pragma unroll
+    for (int c = 0; c < D; ++c) ub[c] = 0.5 * weight * ubar_c<D>(u, N, s, c);
     const double ir = 1.0 / (double)rho[cell];
     double uc[3] = {0, 0, 0};
 #pragma unroll
