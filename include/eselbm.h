@@ -293,6 +293,25 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
                                   const void *seed_next, void *lam_n, double tau, void *force_grad,
                                   void *stream);
 
+/* One adjoint step (eselbm_adjoint_step) whose adjoint of the state after
+ * the step includes the seed of that state's dissipation loss, formed in the
+ * step's kernel from the state's velocity and density field (not in the
+ * paper).  It replaces eselbm_dissipation_loss_uv(uv_next, seed, weight,
+ * force_grad) followed by eselbm_adjoint_step(..., seed_next = seed, ...)
+ * without the seed pass and its buffer: lam_n is the same to the bit, and
+ * force_grad receives the same two contributions, summed in another order.
+ *   uv_next:  device float [D + 1][cells], the velocity and density field of
+ *             the state at step n+1 as eselbm_set_velocity_field receives it
+ *             (with a force registered, u includes the half-force shift,
+ *             whose part of dL/dF is ADDED to force_grad as well).
+ *   weight:   the loss weight w of L = w sum_x |omega(x)|^2 (finite).
+ * Other arguments as eselbm_adjoint_step; lam_n must not alias uv_next.
+ * Supported for ESELBM_F32 and ESELBM_F32_SHIFTED in modes HIGHER, LOWER and
+ * BGK on periodic grids (ESELBM_E_UNSUPPORTED otherwise). */
+eselbm_status eselbm_adjoint_step_diss(eselbm_handle h, const void *f_n, const void *lam_next,
+                                       const float *uv_next, double weight, void *lam_n, double tau,
+                                       void *force_grad, void *stream);
+
 /* Kinetic-energy loss and its seed (not in the paper):
  * L = sum_x rho |u|^2 / 2 of state f.  The value is ADDED to *loss_dev (a
  * device double), summed in a fixed order (the same bits on every run).

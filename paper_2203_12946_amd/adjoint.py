@@ -15,10 +15,11 @@ schedules them:
   segment but the last it recomputes the segment's states from its
   checkpoint (with their velocity fields); the last segment's were kept by
   the forward sweep.  It then applies the adjoint step kernel from the
-  segment's last state down to the first.  The per-step loss seeds travel in
-  compact per-cell form (dL/df_i = s0 + c_i.s) and each is added by the
-  adjoint step that reads it.  The adjoint kernel also accumulates the
-  body-force gradient.
+  segment's last state down to the first.  Each state's loss seed
+  (dL/df_i = s0 + c_i.s) is added by the adjoint step that reads it; in
+  single precision that step forms the seed itself from the state's
+  velocity field, otherwise a seed pass writes it in compact form first.
+  The adjoint kernel also accumulates the body-force gradient.
 
 ``GraphedRollout`` captures a rollout's forward and backward sweeps in two
 HIP graphs for grids small enough that launches dominate.
@@ -116,17 +117,32 @@ class Rollout:
             lam.copy_(lam_final)
         other = s.empty_adjoint()
         w = None if self.diss_weight is None else self.diss_weight * float(diss_grad)
-        # The loss seed of state f^n is kept in compact per-cell form and
-        # added by the adjoint step that reads lambda^n (the next one down).
+        # The loss seed of state f^n enters the adjoint step that reads
+        # lambda^n (the next one down).  In single precision that step forms
+        # it itself from f^n's velocity field (pend_uv); otherwise a seed
+        # pass writes it in compact per-cell form (pend_seed) and the step
+        # adds it.
+        fused = bool(w) and s.compute_dtype == torch.float32
         seed = s.empty_seed() if w else None
-        pending = None
+        pend_seed = pend_uv = None
+
+        def seed_of(f_state, uv):
+            nonlocal pend_seed, pend_uv
+            if fused and uv is not None:
+                pend_uv = uv
+            elif uv is not None:
+                s.dissipation_loss_uv(uv, seed=seed, weight=w, force_grad=force_grad)
+                pend_seed = seed
+            else:
+                s.dissipation_seed(f_state, seed, weight=w, force_grad=force_grad)
+                pend_seed = seed
+
         n_end = self.nsteps
         if w:
             if self.uv_end is not None:
-                s.dissipation_loss_uv(self.uv_end, seed=seed, weight=w, force_grad=force_grad)
+                seed_of(None, self.uv_end)
             else:
-                s.dissipation_seed(self._state_at_end(), seed, weight=w, force_grad=force_grad)
-            pending = seed
+                seed_of(self._state_at_end(), None)
         last = self._last_start()
         for start in sorted(self.ckpts, reverse=True):
             stop = min(start + self.K, n_end)
@@ -156,15 +172,14 @@ class Rollout:
                 self.tail = {}
             for n in range(stop - 1, start - 1, -1):
                 f_n = states[n - start]
-                s.adjoint_step(f_n, lam, other, self.tau, force_grad=force_grad, seed_next=pending)
+                if pend_uv is not None:
+                    s.adjoint_step_diss(f_n, lam, pend_uv, w, other, self.tau, force_grad=force_grad)
+                else:
+                    s.adjoint_step(f_n, lam, other, self.tau, force_grad=force_grad, seed_next=pend_seed)
                 lam, other = other, lam
-                pending = None
+                pend_seed = pend_uv = None
                 if w and n >= 1:
-                    if uvs[n - start] is not None:
-                        s.dissipation_loss_uv(uvs[n - start], seed=seed, weight=w, force_grad=force_grad)
-                    else:
-                        s.dissipation_seed(f_n, seed, weight=w, force_grad=force_grad)
-                    pending = seed
+                    seed_of(f_n, uvs[n - start])
             del states, uvs
             n_end = start
         return lam

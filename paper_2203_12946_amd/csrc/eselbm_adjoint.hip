@@ -129,6 +129,125 @@ __device__ inline void contract_eq(const T (&l)[Lat<D>::Q], const T (&F)[3][3], 
         }
 }
 
+// Periodic neighbourhood of a lane's cell, for the (x-block, y, z) launch:
+// the cell at (dx, dy, dz) from it, |dx|, |dy|, |dz| <= 2, on any grid
+// (extents 1 and 2 included), addressed as a block-uniform row start plus
+// the lane's 32-bit x.
+struct Stencil {
+    unsigned xs[5];        // x of the offsets -2..2
+    long long rows[5][5];  // [dz + 2][dy + 2]: element offset of the row start
+    bool in;
+    __device__ Stencil(const Grid &g)
+    {
+        const int nx = g.nx, ny = g.ny, nz = g.nz;
+        const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+        in = x < nx;
+        const int y = (int)blockIdx.y, z = (int)blockIdx.z;
+        // v in [c - 2, c + 2] with c in [0, n): n is added or subtracted at
+        // most twice (twice only when n is 1 or 2)
+        auto wrap = [](int v, int n) {
+            if (v < 0) v += n;
+            if (v < 0) v += n;
+            if (v >= n) v -= n;
+            if (v >= n) v -= n;
+            return v;
+        };
+        int ys[5], zs[5];
+#pragma unroll
+        for (int o = 0; o < 5; ++o) {
+            xs[o] = (unsigned)wrap(x + o - 2, nx);
+            ys[o] = wrap(y + o - 2, ny);
+            zs[o] = wrap(z + o - 2, nz);
+        }
+#pragma unroll
+        for (int a = 0; a < 5; ++a)
+#pragma unroll
+            for (int b = 0; b < 5; ++b) rows[a][b] = ((long long)zs[a] * ny + ys[b]) * nx;
+    }
+    // the value of a field (its start: f) at the offset
+    __device__ float at(const float *__restrict__ f, int dx, int dy, int dz) const
+    {
+        return *lane_ptr(f + rows[dz + 2][dy + 2], xs[dx + 2]);
+    }
+    __device__ long long cell() const { return rows[2][2] + xs[2]; }
+};
+
+// vorticity component k = (a, b): omega_k = d_a u_b - d_b u_a
+__device__ constexpr int vort_a(int D, int k) { return D == 2 ? 0 : (k == 0 ? 1 : (k == 1 ? 2 : 0)); }
+__device__ constexpr int vort_b(int D, int k) { return D == 2 ? 1 : (k == 0 ? 2 : (k == 1 ? 0 : 1)); }
+
+// omega_k at the cell offset o = (ox, oy, oz) from the lane's cell
+template <int D, int K>
+__device__ inline double omega_at(const float *__restrict__ u, long long N, const Stencil &s, int ox, int oy, int oz)
+{
+    constexpr int a = vort_a(D, K), b = vort_b(D, K);
+    const int o[3] = {ox, oy, oz};
+    int p[3] = {o[0], o[1], o[2]}, m[3] = {o[0], o[1], o[2]};
+    p[a] += 1;
+    m[a] -= 1;
+    const double dub = 0.5 * ((double)s.at(u + b * N, p[0], p[1], p[2]) - (double)s.at(u + b * N, m[0], m[1], m[2]));
+    int q[3] = {o[0], o[1], o[2]}, r[3] = {o[0], o[1], o[2]};
+    q[b] += 1;
+    r[b] -= 1;
+    const double dua = 0.5 * ((double)s.at(u + a * N, q[0], q[1], q[2]) - (double)s.at(u + a * N, r[0], r[1], r[2]));
+    return dub - dua;
+}
+
+// ubar = dL/du(x) for L = w sum_y |curl u(y)|^2, curl taken with the
+// periodic central difference D_a f(y) = (f(y + e_a) - f(y - e_a)) / 2.  D_a
+// is antisymmetric and the D_a commute, so curl is self-adjoint and
+//   ubar = 2 w curl curl u = 2 w (grad div u - sum_a D_a D_a u),
+//   ubar_c = (w / 2) sum_{a != c} [u_a(x + e_c + e_a) - u_a(x + e_c - e_a)
+//            - u_a(x - e_c + e_a) + u_a(x - e_c - e_a)
+//            - u_c(x + 2 e_a) + 2 u_c(x) - u_c(x - 2 e_a)]
+// (the a = c terms of the two operators cancel): 6 D - 5 loads per
+// component instead of the vorticity at four neighbours per term.
+template <int D>
+__device__ inline double ubar_c(const float *__restrict__ u, long long N, const Stencil &s, int c)
+{
+    const float *uc = u + (long long)c * N;
+    const double u0 = (double)s.at(uc, 0, 0, 0);
+    double t = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+        if (a == c) continue;
+        const float *ua = u + (long long)a * N;
+        int p[3] = {0, 0, 0}, m[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
+        p[c] = 1;
+        m[c] = -1;
+        const int pa[3] = {p[0] + (a == 0), p[1] + (a == 1), p[2] + (a == 2)};
+        const int pb[3] = {p[0] - (a == 0), p[1] - (a == 1), p[2] - (a == 2)};
+        const int ma[3] = {m[0] + (a == 0), m[1] + (a == 1), m[2] + (a == 2)};
+        const int mb[3] = {m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2)};
+        e2[a] = 2;
+        const double cross = ((double)s.at(ua, pa[0], pa[1], pa[2]) - (double)s.at(ua, pb[0], pb[1], pb[2])) -
+                             ((double)s.at(ua, ma[0], ma[1], ma[2]) - (double)s.at(ua, mb[0], mb[1], mb[2]));
+        const double lap = ((double)s.at(uc, e2[0], e2[1], e2[2]) - u0) + ((double)s.at(uc, -e2[0], -e2[1], -e2[2]) - u0);
+        t += cross - lap;
+    }
+    return t;
+}
+
+// The dissipation loss's adjoint at the lane's cell from the velocity field
+// u ([D][N]) and density rho: ub = dL/du, ubu = ub . u and ir = 1 / rho.
+// With du_c/df_i = (c_ic - u_c) / rho the seed is dL/df_i = s0 + c_i . s,
+// s0 = -ubu ir and s = ub ir; through the half-force shift of u the direct
+// part of dL/dF is ub ir / 2.  The seed pass and the adjoint step that forms
+// the seed itself both take it from here, so they agree to the bit.
+template <int D>
+__device__ inline void diss_adjoint_at(const float *__restrict__ u, const float *__restrict__ rho, long long N,
+                                       double weight, const Stencil &s, double (&ub)[3], double &ubu, double &ir)
+{
+    const long long cell = s.cell();
+    ub[0] = ub[1] = ub[2] = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) ub[c] = 0.5 * weight * ubar_c<D>(u, N, s, c);
+    ir = 1.0 / (double)rho[cell];
+    ubu = 0.0;
+#pragma unroll
+    for (int c = 0; c < D; ++c) ubu += ub[c] * (double)u[c * N + cell];
+}
+
 // Reverse of the positive root s of -A s^2 + B s - C = 0 given sbar:
 // returns (Abar, Bbar, Cbar) scale factors.
 template <typename T>
@@ -229,6 +348,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
         for (int c = 0; c < 4; ++c) {
             const T sv = c <= D ? sp[(long long)c * N + row0 + x] : T(0);
             sd[c] = seed ? sv : T(0);
+        }
+    }
+    // Or the kernel forms the dissipation seed itself, from the velocity and
+    // density field of the state after the step, as the seed pass would
+    // (the same values to the bit), with the direct half-force part of
+    // dL/dF (fgh), in place of a seed pass and its read here.
+    float fgh[3] = {0.f, 0.f, 0.f};
+    if constexpr (!std::is_same<T, double>::value) {
+        if (a.seed_uv) {
+            const Stencil st(a.g);
+            double ub[3], ubu, irs;
+            diss_adjoint_at<D>(a.seed_uv, a.seed_uv + (long long)D * N, N, a.seed_w, st, ub, ubu, irs);
+            sd[0] = (T)(-ubu * irs);
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                sd[1 + c] = (T)(ub[c] * irs);
+                fgh[c] = (float)(0.5 * ub[c] * irs);
+            }
         }
     }
     // the force gradient accumulated so far, read at the start for the same
@@ -537,7 +674,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
                 const T fb = rho * slfg[c];
                 ubf[c] = fb;
                 rhob -= fb * Fc[c] * ir * ir;
-                if (a.force_grad) a.force_grad[(long long)c * N + row0 + x] = fg0[c] + (float)(fb * ir + sd[1 + c]);
+                if (a.force_grad) {
+                    float v = fg0[c] + (float)(fb * ir + sd[1 + c]);
+                    if (a.seed_uv) v += fgh[c];
+                    a.force_grad[(long long)c * N + row0 + x] = v;
+                }
             }
         }
 #pragma unroll
@@ -707,6 +848,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(adj_waves<S
                 if (Lat<D>::c(i, c) < 0) m -= sd[1 + c];
             }
             push(i, m);
+        }
+        // the step adds no force here, but the velocity of the state after
+        // it still carries the half-force shift
+        if constexpr (FORCE) {
+            if (a.force_grad && a.seed_uv) {
+#pragma unroll
+                for (int c = 0; c < D; ++c) a.force_grad[(long long)c * N + row0 + x] = fg0[c] + fgh[c];
+            }
         }
     }
 }
@@ -936,70 +1085,6 @@ __global__ __launch_bounds__(256) void k_velocity(Grid g, const S *__restrict__ 
     }
 }
 
-// Periodic neighbourhood of a lane's cell, for the (x-block, y, z) launch:
-// the cell at (dx, dy, dz) from it, |dx|, |dy|, |dz| <= 2, on any grid
-// (extents 1 and 2 included), addressed as a block-uniform row start plus
-// the lane's 32-bit x.
-struct Stencil {
-    unsigned xs[5];        // x of the offsets -2..2
-    long long rows[5][5];  // [dz + 2][dy + 2]: element offset of the row start
-    bool in;
-    __device__ Stencil(const Grid &g)
-    {
-        const int nx = g.nx, ny = g.ny, nz = g.nz;
-        const int x = (int)(blockIdx.x * blockDim.x + threadIdx.x);
-        in = x < nx;
-        const int y = (int)blockIdx.y, z = (int)blockIdx.z;
-        // v in [c - 2, c + 2] with c in [0, n): n is added or subtracted at
-        // most twice (twice only when n is 1 or 2)
-        auto wrap = [](int v, int n) {
-            if (v < 0) v += n;
-            if (v < 0) v += n;
-            if (v >= n) v -= n;
-            if (v >= n) v -= n;
-            return v;
-        };
-        int ys[5], zs[5];
-#pragma unroll
-        for (int o = 0; o < 5; ++o) {
-            xs[o] = (unsigned)wrap(x + o - 2, nx);
-            ys[o] = wrap(y + o - 2, ny);
-            zs[o] = wrap(z + o - 2, nz);
-        }
-#pragma unroll
-        for (int a = 0; a < 5; ++a)
-#pragma unroll
-            for (int b = 0; b < 5; ++b) rows[a][b] = ((long long)zs[a] * ny + ys[b]) * nx;
-    }
-    // the value of a field (its start: f) at the offset
-    __device__ float at(const float *__restrict__ f, int dx, int dy, int dz) const
-    {
-        return *lane_ptr(f + rows[dz + 2][dy + 2], xs[dx + 2]);
-    }
-    __device__ long long cell() const { return rows[2][2] + xs[2]; }
-};
-
-// vorticity component k = (a, b): omega_k = d_a u_b - d_b u_a
-__device__ constexpr int vort_a(int D, int k) { return D == 2 ? 0 : (k == 0 ? 1 : (k == 1 ? 2 : 0)); }
-__device__ constexpr int vort_b(int D, int k) { return D == 2 ? 1 : (k == 0 ? 2 : (k == 1 ? 0 : 1)); }
-
-// omega_k at the cell offset o = (ox, oy, oz) from the lane's cell
-template <int D, int K>
-__device__ inline double omega_at(const float *__restrict__ u, long long N, const Stencil &s, int ox, int oy, int oz)
-{
-    constexpr int a = vort_a(D, K), b = vort_b(D, K);
-    const int o[3] = {ox, oy, oz};
-    int p[3] = {o[0], o[1], o[2]}, m[3] = {o[0], o[1], o[2]};
-    p[a] += 1;
-    m[a] -= 1;
-    const double dub = 0.5 * ((double)s.at(u + b * N, p[0], p[1], p[2]) - (double)s.at(u + b * N, m[0], m[1], m[2]));
-    int q[3] = {o[0], o[1], o[2]}, r[3] = {o[0], o[1], o[2]};
-    q[b] += 1;
-    r[b] -= 1;
-    const double dua = 0.5 * ((double)s.at(u + a * N, q[0], q[1], q[2]) - (double)s.at(u + a * N, r[0], r[1], r[2]));
-    return dub - dua;
-}
-
 // The loss alone: weight * sum_x |omega(x)|^2, one partial sum per block.
 // (Forming the total in the same launch, the last block to finish adding the
 // partials after a counter of finished blocks, measured 20 times slower: the
@@ -1022,41 +1107,6 @@ __global__ __launch_bounds__(256) void k_diss_loss(Grid g, const float *__restri
     block_partial(e, part, ((long long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x);
 }
 
-// ubar = dL/du(x) for L = w sum_y |curl u(y)|^2, curl taken with the
-// periodic central difference D_a f(y) = (f(y + e_a) - f(y - e_a)) / 2.  D_a
-// is antisymmetric and the D_a commute, so curl is self-adjoint and
-//   ubar = 2 w curl curl u = 2 w (grad div u - sum_a D_a D_a u),
-//   ubar_c = (w / 2) sum_{a != c} [u_a(x + e_c + e_a) - u_a(x + e_c - e_a)
-//            - u_a(x - e_c + e_a) + u_a(x - e_c - e_a)
-//            - u_c(x + 2 e_a) + 2 u_c(x) - u_c(x - 2 e_a)]
-// (the a = c terms of the two operators cancel): 6 D - 5 loads per
-// component instead of the vorticity at four neighbours per term.
-template <int D>
-__device__ inline double ubar_c(const float *__restrict__ u, long long N, const Stencil &s, int c)
-{
-    const float *uc = u + (long long)c * N;
-    const double u0 = (double)s.at(uc, 0, 0, 0);
-    double t = 0.0;
-#pragma unroll
-    for (int a = 0; a < D; ++a) {
-        if (a == c) continue;
-        const float *ua = u + (long long)a * N;
-        int p[3] = {0, 0, 0}, m[3] = {0, 0, 0}, e2[3] = {0, 0, 0};
-        p[c] = 1;
-        m[c] = -1;
-        const int pa[3] = {p[0] + (a == 0), p[1] + (a == 1), p[2] + (a == 2)};
-        const int pb[3] = {p[0] - (a == 0), p[1] - (a == 1), p[2] - (a == 2)};
-        const int ma[3] = {m[0] + (a == 0), m[1] + (a == 1), m[2] + (a == 2)};
-        const int mb[3] = {m[0] - (a == 0), m[1] - (a == 1), m[2] - (a == 2)};
-        e2[a] = 2;
-        const double cross = ((double)s.at(ua, pa[0], pa[1], pa[2]) - (double)s.at(ua, pb[0], pb[1], pb[2])) -
-                             ((double)s.at(ua, ma[0], ma[1], ma[2]) - (double)s.at(ua, mb[0], mb[1], mb[2]));
-        const double lap = ((double)s.at(uc, e2[0], e2[1], e2[2]) - u0) + ((double)s.at(uc, -e2[0], -e2[1], -e2[2]) - u0);
-        t += cross - lap;
-    }
-    return t;
-}
-
 template <int D, typename T>
 __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restrict__ u, const float *__restrict__ rho,
                                                    T *lam, T *seed, double weight, float *force_grad)
@@ -1065,18 +1115,8 @@ __global__ __launch_bounds__(256) void k_diss_seed(Grid g, const float *__restri
     const Stencil s(g);
     if (!s.in) return;
     const long long N = g.N, cell = s.cell();
-    double ub[3] = {0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < D; ++c) ub[c] = 0.5 * weight * ubar_c<D>(u, N, s, c);
-    const double ir = 1.0 / (double)rho[cell];
-    double uc[3] = {0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < D; ++c) uc[c] = (double)u[c * N + cell];
-    // du_c/df_i = (c_ic - u_c) / rho: dL/df_i = s0 + c_i . s with
-    // s0 = -ubar . u / rho and s = ubar / rho
-    double ubu = 0.0;
-#pragma unroll
-    for (int c = 0; c < D; ++c) ubu += ub[c] * uc[c];
+    double ub[3], ubu, ir;
+    diss_adjoint_at<D>(u, rho, N, weight, s, ub, ubu, ir);
     if (seed) {
         seed[cell] = (T)(-ubu * ir);
 #pragma unroll

@@ -47,6 +47,9 @@ static eselbm_status hip_fail(hipError_t e, const char *where)
     return ESELBM_E_HIP;
 }
 
+static eselbm_status fail(eselbm_status st, const std::string &msg) { return fail(st, msg.c_str()); }
+static eselbm_status hip_fail(hipError_t e, const std::string &where) { return hip_fail(e, where.c_str()); }
+
 // The handle's device memory, and the caller's buffers and stream that go
 // with it, belong to the device that was current at eselbm_create; a call
 // made with another device current would launch there on foreign pointers.
@@ -367,20 +370,24 @@ eselbm_status eselbm_moments(eselbm_handle h, const void *f, double *rho, double
     return ESELBM_OK;
 }
 
-eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next, const void *seed_next,
-                                  void *lam_n, double tau, void *force_grad, void *stream)
+// The adjoint step behind both entry points: the loss seed of the state
+// after the step, if any, comes as a compact seed (seed_next) or as that
+// state's velocity field (seed_uv), whose dissipation seed the kernel forms.
+static eselbm_status adjoint_step_impl(eselbm_handle h, const void *f_n, const void *lam_next, const void *seed_next,
+                                       const float *seed_uv, double seed_w, void *lam_n, double tau, void *force_grad,
+                                       void *stream, const char *who)
 {
-    if (!h || !f_n || !lam_next || !lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: NULL argument");
-    if (eselbm_status st = device_check(h, "eselbm_adjoint_step")) return st;
-    if (lam_next == lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: lam_n must not alias lam_next");
-    if (seed_next && seed_next == lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: lam_n must not alias seed_next");
-    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: tau must be finite and > 0");
-    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: F16 storage has no adjoint");
-    if (force_grad && !h->force) return fail(ESELBM_E_ARG, "eselbm_adjoint_step: force_grad without a registered force");
+    if (!h || !f_n || !lam_next || !lam_n) return fail(ESELBM_E_ARG, std::string(who) + ": NULL argument");
+    if (eselbm_status st = device_check(h, who)) return st;
+    if (lam_next == lam_n) return fail(ESELBM_E_ARG, std::string(who) + ": lam_n must not alias lam_next");
+    if (seed_next && seed_next == lam_n) return fail(ESELBM_E_ARG, std::string(who) + ": lam_n must not alias seed_next");
+    if (!(tau > 0.0) || !std::isfinite(tau)) return fail(ESELBM_E_ARG, std::string(who) + ": tau must be finite and > 0");
+    if (h->dtype == ESELBM_F16_SHIFTED) return fail(ESELBM_E_UNSUPPORTED, std::string(who) + ": F16 storage has no adjoint");
+    if (force_grad && !h->force) return fail(ESELBM_E_ARG, std::string(who) + ": force_grad without a registered force");
     if (h->mode == ESELBM_MODE_ELBM || h->mode == ESELBM_MODE_ITERATE1 || h->mode == ESELBM_MODE_LBGK)
-        return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the ELBM, Iterate1 and classic LBGK modes");
-    if (h->walls) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: the adjoint is periodic only");
-    if (h->prandtl != 1.0) return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step: no adjoint of the ES-BGK collision");
+        return fail(ESELBM_E_UNSUPPORTED, std::string(who) + ": no adjoint of the ELBM, Iterate1 and classic LBGK modes");
+    if (h->walls) return fail(ESELBM_E_UNSUPPORTED, std::string(who) + ": the adjoint is periodic only");
+    if (h->prandtl != 1.0) return fail(ESELBM_E_UNSUPPORTED, std::string(who) + ": no adjoint of the ES-BGK collision");
     AdjArgs a;
     a.fn = f_n;
     a.lam_next = lam_next;
@@ -390,9 +397,30 @@ eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *
     a.force = h->force;
     a.force_grad = (float *)force_grad;
     a.seed = seed_next;
+    a.seed_uv = seed_uv;
+    a.seed_w = seed_w;
     hipError_t e = launch_adjoint(h->dtype, h->mode, a, (hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "eselbm_adjoint_step: launch");
+    if (e != hipSuccess) return hip_fail(e, std::string(who) + ": launch");
     return ESELBM_OK;
+}
+
+eselbm_status eselbm_adjoint_step(eselbm_handle h, const void *f_n, const void *lam_next, const void *seed_next,
+                                  void *lam_n, double tau, void *force_grad, void *stream)
+{
+    return adjoint_step_impl(h, f_n, lam_next, seed_next, nullptr, 0.0, lam_n, tau, force_grad, stream,
+                             "eselbm_adjoint_step");
+}
+
+eselbm_status eselbm_adjoint_step_diss(eselbm_handle h, const void *f_n, const void *lam_next, const float *uv_next,
+                                       double weight, void *lam_n, double tau, void *force_grad, void *stream)
+{
+    if (!h || !uv_next) return fail(ESELBM_E_ARG, "eselbm_adjoint_step_diss: NULL argument");
+    if (!std::isfinite(weight)) return fail(ESELBM_E_ARG, "eselbm_adjoint_step_diss: weight must be finite");
+    if (h->dtype != ESELBM_F32 && h->dtype != ESELBM_F32_SHIFTED)
+        return fail(ESELBM_E_UNSUPPORTED, "eselbm_adjoint_step_diss: single-precision adjoints only (F32, F32-shifted)");
+    if (uv_next == (const float *)lam_n) return fail(ESELBM_E_ARG, "eselbm_adjoint_step_diss: lam_n must not alias uv_next");
+    return adjoint_step_impl(h, f_n, lam_next, nullptr, uv_next, weight, lam_n, tau, force_grad, stream,
+                             "eselbm_adjoint_step_diss");
 }
 
 eselbm_status eselbm_kinetic_loss(eselbm_handle h, const void *f, double *loss_dev, void *lam, double scale,

@@ -64,6 +64,11 @@ struct AdjArgs {
     const float *force;
     float *force_grad;
     const void *seed;  // compute type [1 + D][N] or null: lam_next_i += s0 + c_i . s
+    // or null; else float [D + 1][N], the velocity and density field of the
+    // state after the step, whose dissipation-loss seed (weight seed_w) the
+    // kernel forms and adds as it would add seed (seed must then be null)
+    const float *seed_uv = nullptr;
+    double seed_w = 0.0;
 };
 hipError_t launch_adjoint(int dtype, int mode, const AdjArgs &a, hipStream_t s);
 // Scratch of the losses, owned by a handle (so by its device) and grown on

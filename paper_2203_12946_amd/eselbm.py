@@ -69,6 +69,7 @@ _SIGNATURES = {
     "eselbm_alpha_stats": [_vp, ctypes.POINTER(Stats), ctypes.c_int, _vp],
     "eselbm_moments": [_vp, _vp, _vp, _vp, _vp],
     "eselbm_adjoint_step": [_vp, _vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
+    "eselbm_adjoint_step_diss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, ctypes.c_double, _vp, _vp],
     "eselbm_kinetic_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
     "eselbm_kinetic_loss_noalloc": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp],
     "eselbm_dissipation_loss": [_vp, _vp, _vp, _vp, ctypes.c_double, _vp, _vp],
@@ -286,6 +287,19 @@ class Solver:
             _check(lib.eselbm_adjoint_step(
                 self._h, self._p(f_n, self.storage_dtype, n), self._p(lam_next, self.compute_dtype, n),
                 self._p(seed_next, self.compute_dtype, (1 + self.D) * self.cells) if seed_next is not None else _vp(None),
+                self._p(lam_n, self.compute_dtype, n), float(tau),
+                self._p(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
+                _stream(stream)))
+
+    def adjoint_step_diss(self, f_n, lam_next, uv_next, weight: float, lam_n, tau: float, force_grad=None,
+                          stream=None):
+        """adjoint_step with the dissipation seed of the state after the step
+        formed in the kernel from that state's velocity field uv_next."""
+        n = self.Q * self.cells
+        with self._on():
+            _check(lib.eselbm_adjoint_step_diss(
+                self._h, self._p(f_n, self.storage_dtype, n), self._p(lam_next, self.compute_dtype, n),
+                self._p(uv_next, torch.float32, (self.D + 1) * self.cells), float(weight),
                 self._p(lam_n, self.compute_dtype, n), float(tau),
                 self._p(force_grad, torch.float32, self.D * self.cells) if force_grad is not None else _vp(None),
                 _stream(stream)))
