@@ -64,4 +64,8 @@ def test_argument_errors_without_device(lib):
     assert lib.eselbm_create(ctypes.byref(h), 1, 1 << 17, 1 << 15, 2, 1) == 2  # 2^33 cells
     assert b"2^32" in lib.eselbm_last_error()
     assert lib.eselbm_step(None, None, None, 1, ctypes.c_double(0.1), None) == 1
+    assert lib.eselbm_adjoint_step(None, None, None, None, None, ctypes.c_double(0.1), None, None) == 1
+    assert lib.eselbm_adjoint_step_diss(None, None, None, None, ctypes.c_double(1.0), None, ctypes.c_double(0.1),
+                                        None, None) == 1
+    assert b"eselbm_adjoint_step_diss" in lib.eselbm_last_error()
     assert lib.eselbm_destroy(None) == 0
