@@ -129,8 +129,12 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
 //    rounding, visible above the shifted floor;
 //  - F16-shifted: storage rounding (1e-3 of the deviation) dwarfs all
 //    arithmetic rounding, and the power series of the path-length sums is
-//    cut at the order that rounding allows (SeriesCfgF16); F64: every part
-//    is double already.
+//    cut at the order that rounding allows (SeriesCfgF16).  It also skips
+//    the exact-moment fix of d (conserve_moments): the bias that fix
+//    removes, about 1e-8 of w per step, lies far below the unbiased storage
+//    rounding of every stored deviation (about 1e-5 of w per step), which
+//    conserves mass and momentum only on average anyway, and the step is
+//    bound by VALU issue; F64: every part is double already.
 // The kernel is a stream of Q loads and Q stores per lane and needs several
 // waves per SIMD in flight to cover HBM latency: 4 waves (<= 128 VGPRs) for
 // the 4- and 2-byte formats; the double moments and equilibrium of
@@ -146,7 +150,7 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
 template <typename S>
 struct StepPolicy {
     static constexpr int waves = 4;
-    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
+    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false, conserve = true;
     static constexpr int stash = 0, stash_waves = 0;
     using Series = SeriesCfg<typename Storage<S>::T>;
     using Exact = double;
@@ -154,7 +158,7 @@ struct StepPolicy {
 template <>
 struct StepPolicy<f32s> {
     static constexpr int waves = 4;
-    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = true;
+    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = true, conserve = true;
     static constexpr int stash = 0, stash_waves = 0;
     using Series = SeriesCfg<float>;
     using Exact = double;
@@ -162,7 +166,7 @@ struct StepPolicy<f32s> {
 template <>
 struct StepPolicy<_Float16> {
     static constexpr int waves = 4;
-    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false;
+    static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false, conserve = false;
     static constexpr int stash = 0, stash_waves = 0;
     using Series = SeriesCfgF16;
     using Exact = float;
@@ -170,7 +174,7 @@ struct StepPolicy<_Float16> {
 template <>
 struct StepPolicy<double> {
     static constexpr int waves = 2;
-    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = false;
+    static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = false, conserve = true;
     static constexpr int stash = 24, stash_waves = 3;
     using Series = SeriesCfg<double>;
     using Exact = double;
@@ -197,10 +201,10 @@ constexpr int stash_pops()
 }
 
 // d = feq - g of one cell, with moments and equilibrium in EQ, rounded to T,
-// and its mass and momentum then made exact to rounding.
+// and (CONSERVE) its mass and momentum then made exact to rounding.
 // With POLY the equilibrium is the polynomial one of Eq. histeq (the classic
 // LBGK mode): feq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)).
-template <int D, typename T, typename EQ, bool POLY, typename Dev>
+template <int D, typename T, typename EQ, bool POLY, bool CONSERVE, typename Dev>
 __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)[Lat<D>::Q])
 {
     const EQ rho = EQ(1) + drho, ir = rcp_(rho);
@@ -225,7 +229,7 @@ __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)
         }
         d[i] = T(fe - EQ(v));
     }
-    conserve_moments<D, T>(d);
+    if constexpr (CONSERVE) conserve_moments<D, T>(d);
 }
 
 // The mirror-condition modes iterate over Q logarithms per Newton step:
@@ -502,7 +506,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
             // fixed function of the cell's state, so it acts as a bias that
             // accumulates over steps.  The path length stays in T.
             using EQ = typename std::conditional<Pol::eq_f64, double, T>::type;
-            form_deviation<D, T, EQ, MODE == MODE_LBGK>(pdev, EQ(drhoE), {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
+            form_deviation<D, T, EQ, MODE == MODE_LBGK, Pol::conserve>(pdev, EQ(drhoE),
+                                                                      {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
             // ES-BGK: the quasi-equilibrium replaces the equilibrium, and the
             // path length is found from x = f^QE / g - 1 as before
             int qe_it = 0;
