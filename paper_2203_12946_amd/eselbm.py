@@ -365,3 +365,18 @@ class Solver:
 
 def beta_of_tau(tau: float) -> float:
     return 1.0 / (2.0 * tau + 1.0)
+
+
+def rollout(solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
+            force: torch.Tensor | None = None, diss_weight: float | None = None):
+    """Differentiable checkpointed rollout: (state after nsteps, accumulated
+    dissipation loss); see paper_2203_12946_amd.adjoint.rollout."""
+    from .adjoint import rollout as _rollout
+    return _rollout(solver, f0, tau, nsteps, ckpt_every, force=force, diss_weight=diss_weight)
+
+
+def equilibrium(solver: Solver, rho: torch.Tensor, u: torch.Tensor) -> torch.Tensor:
+    """Differentiable equilibrium initial state f = feq(rho, u) (gradient
+    w.r.t. u); see paper_2203_12946_amd.adjoint.equilibrium."""
+    from .adjoint import equilibrium as _equilibrium
+    return _equilibrium(solver, rho, u)
