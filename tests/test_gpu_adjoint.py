@@ -537,3 +537,22 @@ def test_compact_seed_matches_full_seed(es, dtype):
     _log(f"[compact seed {dtype}] expand err {np.max(np.abs(expanded - full.double().cpu().numpy())) / scale:.2e}, "
          f"seeded-step err {err:.2e}")
     assert err <= (1e-13 if dtype == "f64" else 1e-6)
+
+
+def test_module_level_wrappers(es):
+    """eselbm.equilibrium and eselbm.rollout are the autograd entry points of
+    paper_2203_12946_amd.adjoint: the same values and gradients."""
+    from paper_2203_12946_amd import adjoint as A
+    N = 24
+    rho, u = W.random_divfree_2d(N, k_peak=3, u_rms=0.03, seed=71)
+    s = es.Solver("D2Q9", (N, N), dtype="f32")
+    r = torch.from_numpy(rho).cuda()
+    grads = []
+    for eq, ro in ((es.equilibrium, es.rollout), (A.equilibrium, A.rollout)):
+        u0 = torch.from_numpy(u).cuda().requires_grad_(True)
+        fN, _ = ro(s, eq(s, r, u0), 1e-3, 9, 4)
+        L = A.kinetic_energy(s, fN)
+        L.backward()
+        grads.append((L.item(), u0.grad.clone()))
+    assert grads[0][0] == grads[1][0]
+    assert torch.equal(grads[0][1], grads[1][1])
