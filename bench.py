@@ -9,7 +9,8 @@ reference the headline is compared with), FP64 storage, FP16-shifted and
 F32-shifted storage, alpha_Lower, the iterative ELBM path length and its
 one-step alpha_Iterate1 (the root search the closed form replaces), the
 per-step alpha statistics of the 64^2 D2Q9 Taylor-Green workload, and the
-adjoint/forward time of the 128^3 forced D3Q27 rollout with checkpointing.
+adjoint/forward time of the 128^3 forced D3Q27 rollout with checkpointing
+(and, beside it, with every state of the rollout kept in HBM instead).
 The FP64 oracle is timed on the host cores on the 64^2 and 1024^2 D2Q9
 workloads and on a slab of the headline one.
 
@@ -273,7 +274,8 @@ def copy_bandwidth(torch, nbytes: int, reps: int = 20):
 def time_adjoint(es, torch, W, steps: int, ckpt: int):
     """Forward rollout (with the per-step dissipation loss) and its adjoint
     sweep (recompute + adjoint kernels + loss seeds) on the forced 128^3
-    D3Q27 workload."""
+    D3Q27 workload, checkpointed every ``ckpt`` steps; then the same with
+    every state kept from the forward (no recompute), where memory allows."""
     from paper_2203_12946_amd.adjoint import Rollout
     wl = W.ADJ3D_128
     rho, u = W.fields_for(wl)
@@ -300,9 +302,35 @@ def time_adjoint(es, torch, W, steps: int, ckpt: int):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     ok = bool(torch.isfinite(fg).all().item())
-    return dict(workload=wl.name, steps=steps, ckpt_every=ckpt, forward_s=t1 - t0, backward_s=t3 - t2,
-                ratio=(t3 - t2) / (t1 - t0), loss=float(loss.item()), grad_finite=ok,
-                grad_norm=float(fg.double().norm().item()))
+    out = dict(workload=wl.name, steps=steps, ckpt_every=ckpt, forward_s=t1 - t0, backward_s=t3 - t2,
+               ratio=(t3 - t2) / (t1 - t0), loss=float(loss.item()), grad_finite=ok,
+               grad_norm=float(fg.double().norm().item()))
+    del ro
+    # The same gradient with every state of the rollout kept in HBM by the
+    # forward (no recomputation in the backward): the memory for compute
+    # trade a 288 GB device affords at this size.
+    ro = Rollout(s, wl.tau, steps, ckpt, diss_weight=nu0, keep_segments=None)
+    state_gb = steps * s.Q * s.cells * 4 / 1e9
+    if torch.cuda.mem_get_info()[0] > 1.3 * (state_gb + steps * 4 * s.cells * 4 / 1e9):
+        ro.forward(f0, loss)
+        ro.backward(None, diss_grad=1.0, force_grad=torch.zeros_like(fg))
+        torch.cuda.synchronize()
+        loss.zero_()
+        t0 = time.perf_counter()
+        ro.forward(f0, loss)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        fg2 = torch.zeros_like(fg)
+        t2 = time.perf_counter()
+        ro.backward(None, diss_grad=1.0, force_grad=fg2)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+        out["all_states_resident"] = dict(
+            forward_s=t1 - t0, backward_s=t3 - t2, ratio=(t3 - t2) / (t1 - t0), state_gb=round(state_gb, 1),
+            grad_equal_checkpointed=bool(torch.equal(fg2, fg)), loss_equal_checkpointed=bool(loss.item() == out["loss"]))
+    del ro
+    torch.cuda.empty_cache()
+    return out
 
 
 def time_adjoint_2d(es, torch, W):
@@ -591,6 +619,10 @@ def main():
         _log("bench: adjoint 128^3")
         adj = time_adjoint(es, torch, W, args.adjoint_steps, 50)
         _log(f"bench: adjoint/forward = {adj['ratio']:.2f}")
+        if "all_states_resident" in adj:
+            r = adj["all_states_resident"]
+            _log(f"bench: adjoint/forward with every state resident ({r['state_gb']} GB) = {r['ratio']:.2f}, "
+                 f"gradient equal to the checkpointed one: {r['grad_equal_checkpointed']}")
         _log("bench: adjoint 256^2")
         adj["d2q9_adjoint_256"] = time_adjoint_2d(es, torch, W)
         a2 = adj["d2q9_adjoint_256"]

@@ -8,13 +8,16 @@ schedules them:
   weight * sum_x |omega|^2 after every step.  The step itself writes the
   velocity and density of its output (the loss depends on the state only
   through them), so the loss reads that field instead of the state.
-  The states of the last segment (those after its checkpoint) are written to
-  buffers of their own and kept, with their velocity fields, as is the
+  The states of the last ``keep_segments`` segments (those after the first
+  kept segment's checkpoint; by default the last segment's only) are written
+  to buffers of their own and kept, with their velocity fields, as is the
   velocity field of every checkpoint: the backward sweep starts from them.
+  ``keep_segments=None`` keeps every state, so that the backward recomputes
+  nothing (at 128^3 D3Q27 in single precision, 500 states take 113 GB of
+  the 288 GB of HBM).
 * ``Rollout.backward`` sweeps the checkpoint segments in reverse.  For each
-  segment but the last it recomputes the segment's states from its
-  checkpoint (with their velocity fields); the last segment's were kept by
-  the forward sweep.  It then applies the adjoint step kernel from the
+  segment whose states were not kept it recomputes them from its checkpoint
+  (with their velocity fields).  It then applies the adjoint step kernel from the
   segment's last state down to the first.  Each state's loss seed
   (dL/df_i = s0 + c_i.s) is added by the adjoint step that reads it; in
   single precision that step forms the seed itself from the state's
@@ -38,14 +41,17 @@ from .eselbm import Solver
 
 class Rollout:
     def __init__(self, solver: Solver, tau: float, nsteps: int, ckpt_every: int,
-                 diss_weight: float | None = None):
+                 diss_weight: float | None = None, keep_segments: int | None = 1):
         if nsteps < 1 or ckpt_every < 1:
             raise ValueError("nsteps and ckpt_every must be >= 1")
+        if keep_segments is not None and int(keep_segments) < 1:
+            raise ValueError("keep_segments must be >= 1 or None")
         self.s = solver
         self.tau = float(tau)
         self.nsteps = int(nsteps)
         self.K = int(ckpt_every)
         self.diss_weight = diss_weight
+        self.keep_segments = None if keep_segments is None else int(keep_segments)
         self.ckpts: dict[int, torch.Tensor] = {}
         # velocity fields of the checkpoints (with the loss), and the states
         # of the last segment after its checkpoint with their velocity fields
@@ -66,6 +72,13 @@ class Rollout:
         """First state of the last checkpoint segment."""
         return ((self.nsteps - 1) // self.K) * self.K
 
+    def _kept_start(self) -> int:
+        """First state (a checkpoint) of the first segment whose states the
+        forward keeps."""
+        if self.keep_segments is None:
+            return 0
+        return max(0, self._last_start() - (self.keep_segments - 1) * self.K)
+
     def forward(self, f0: torch.Tensor, loss_acc: torch.Tensor | None = None) -> torch.Tensor:
         """State after nsteps; with a dissipation weight, adds the loss of
         every state f^1..f^n to ``loss_acc`` (a device float64 scalar)."""
@@ -76,17 +89,18 @@ class Rollout:
         self.ckpts[0] = cur.clone()
         with_loss = self.diss_weight is not None and loss_acc is not None
         uv = s.empty_velocity() if with_loss else None
-        last = self._last_start()
+        first = self._kept_start()
         for n in range(self.nsteps):
             m = n + 1  # the state this step produces
-            # the states after the last checkpoint, and the final one, get
-            # buffers of their own (the former are kept for the backward)
-            fresh = m > last
-            keep = last < m < self.nsteps
+            # the states after the first kept segment's checkpoint, and the
+            # final one, get buffers of their own (the former are kept for
+            # the backward)
+            fresh = m > first
+            keep = first < m < self.nsteps
             out = s.empty_state() if fresh else nxt
             out_uv = None
             if with_loss:
-                out_uv = s.empty_velocity() if (keep or m == last) else uv
+                out_uv = s.empty_velocity() if (keep or m == first) else uv
                 self._step_with_velocity(cur, out, out_uv)
                 s.dissipation_loss_uv(out_uv, loss=loss_acc, weight=self.diss_weight)
             else:
@@ -95,12 +109,13 @@ class Rollout:
                 cur = out
             else:
                 cur, nxt = out, cur
-            if keep:
+            if keep and m % self.K != 0:
                 self.tail[m] = (out, out_uv)
             if m % self.K == 0 and m < self.nsteps:
-                self.ckpts[m] = cur.clone()
+                # a kept state's buffer is never written again
+                self.ckpts[m] = cur if fresh else cur.clone()
                 if with_loss:
-                    self.ckpt_uv[m] = out_uv if m == last else out_uv.clone()
+                    self.ckpt_uv[m] = out_uv if (keep or m == first) else out_uv.clone()
         if with_loss:
             self.uv_end = out_uv
         return cur
@@ -143,14 +158,13 @@ class Rollout:
                 seed_of(None, self.uv_end)
             else:
                 seed_of(self._state_at_end(), None)
-        last = self._last_start()
         for start in sorted(self.ckpts, reverse=True):
             stop = min(start + self.K, n_end)
             # states f^start .. f^(stop-1) and, with the loss, the velocity
             # field of each (None where only the state is at hand)
             states = [self.ckpts[start]]
             uvs = [self.ckpt_uv.get(start)]
-            kept = start == last and all(m in self.tail for m in range(start + 1, stop))
+            kept = all(m in self.tail for m in range(start + 1, stop))
             for m in range(start + 1, stop):
                 if kept:
                     states.append(self.tail[m][0])
@@ -166,10 +180,10 @@ class Rollout:
                 states.append(nxt)
             if kept:
                 # the kept states now live in this segment's list only, so
-                # they are freed with it: the backward's memory peak stays at
-                # one segment of states (a later backward of the same forward
-                # recomputes them)
-                self.tail = {}
+                # they are freed with it, segment by segment (a later
+                # backward of the same forward recomputes them)
+                for m in range(start + 1, stop):
+                    del self.tail[m]
             for n in range(stop - 1, start - 1, -1):
                 f_n = states[n - start]
                 if pend_uv is not None:
@@ -219,9 +233,10 @@ class GraphedRollout:
     """
 
     def __init__(self, solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
-                 diss_weight: float | None = None, diss_grad: float = 1.0, with_force_grad: bool = False):
+                 diss_weight: float | None = None, diss_grad: float = 1.0, with_force_grad: bool = False,
+                 keep_segments: int | None = 1):
         s = solver
-        self.ro = Rollout(s, tau, nsteps, ckpt_every, diss_weight)
+        self.ro = Rollout(s, tau, nsteps, ckpt_every, diss_weight, keep_segments)
         self.f0 = f0.detach().clone()
         self.lam_final = s.empty_adjoint().zero_()
         self.loss = torch.zeros(1, dtype=torch.float64, device=s.device)
@@ -284,12 +299,12 @@ class _Equilibrium(torch.autograd.Function):
 
 class _Rollout(torch.autograd.Function):
     @staticmethod
-    def forward(ctx, f0, force, solver, tau, nsteps, ckpt_every, diss_weight):
+    def forward(ctx, f0, force, solver, tau, nsteps, ckpt_every, diss_weight, keep_segments):
         # the rollout's force replaces whatever the solver had registered
         # (None clears it), so the forward never runs with a stale force that
         # the backward would not differentiate
         solver.set_force(None if force is None else force.detach().contiguous())
-        ro = Rollout(solver, tau, nsteps, ckpt_every, diss_weight)
+        ro = Rollout(solver, tau, nsteps, ckpt_every, diss_weight, keep_segments)
         loss = torch.zeros(1, dtype=torch.float64, device=f0.device)
         fN = ro.forward(f0.detach().contiguous(), loss if diss_weight is not None else None)
         ctx.ro = ro
@@ -306,7 +321,7 @@ class _Rollout(torch.autograd.Function):
         lamN = None if g_fN is None else g_fN.to(s.compute_dtype).contiguous()
         dl = 0.0 if g_loss is None else float(g_loss)
         lam0 = ro.backward(lamN, diss_grad=dl, force_grad=fg)
-        return lam0, fg, None, None, None, None, None
+        return lam0, fg, None, None, None, None, None, None
 
 
 class _Kinetic(torch.autograd.Function):
@@ -332,10 +347,13 @@ def equilibrium(solver: Solver, rho: torch.Tensor, u: torch.Tensor) -> torch.Ten
 
 
 def rollout(solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
-            force: torch.Tensor | None = None, diss_weight: float | None = None):
+            force: torch.Tensor | None = None, diss_weight: float | None = None,
+            keep_segments: int | None = 1):
     """(state after nsteps, accumulated dissipation loss).  ``force`` becomes
-    the solver's registered body force for the rollout; None clears it."""
-    return _Rollout.apply(f0, force, solver, tau, nsteps, ckpt_every, diss_weight)
+    the solver's registered body force for the rollout; None clears it.
+    ``keep_segments``: the trailing checkpoint segments whose states the
+    forward keeps for the backward (None: all of them, no recomputation)."""
+    return _Rollout.apply(f0, force, solver, tau, nsteps, ckpt_every, diss_weight, keep_segments)
 
 
 def kinetic_energy(solver: Solver, f: torch.Tensor) -> torch.Tensor:

@@ -368,11 +368,13 @@ def beta_of_tau(tau: float) -> float:
 
 
 def rollout(solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
-            force: torch.Tensor | None = None, diss_weight: float | None = None):
+            force: torch.Tensor | None = None, diss_weight: float | None = None,
+            keep_segments: int | None = 1):
     """Differentiable checkpointed rollout: (state after nsteps, accumulated
     dissipation loss); see paper_2203_12946_amd.adjoint.rollout."""
     from .adjoint import rollout as _rollout
-    return _rollout(solver, f0, tau, nsteps, ckpt_every, force=force, diss_weight=diss_weight)
+    return _rollout(solver, f0, tau, nsteps, ckpt_every, force=force, diss_weight=diss_weight,
+                    keep_segments=keep_segments)
 
 
 def equilibrium(solver: Solver, rho: torch.Tensor, u: torch.Tensor) -> torch.Tensor:

@@ -442,10 +442,12 @@ def test_rollout_schedules_agree(es, dtype):
     rollout with the dissipation loss over 7 steps, checkpointed every 1, 4
     and 20 steps (every state a checkpoint; a last segment of three states,
     two of them kept by the forward; one segment that the forward keeps
-    whole), gives the same bits, and so does a second backward of one forward
-    (it recomputes the states the first one used and released).  In single
-    precision, with a body force, the adjoint steps form the loss seeds
-    themselves; in double precision, unforced, seed passes write them."""
+    whole), and every 2 steps with the last two segments kept or every state
+    kept (no recomputation), gives the same bits, and so does a second
+    backward of one forward (it recomputes the states the first one used and
+    released).  In single precision, with a body force, the adjoint steps form
+    the loss seeds themselves; in double precision, unforced, seed passes
+    write them."""
     from paper_2203_12946_amd.adjoint import Rollout
     shape = (5, 6, 70)
     n = 7
@@ -457,21 +459,28 @@ def test_rollout_schedules_agree(es, dtype):
         s.set_force(F)
     f0 = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
     results = []
-    for ckpt in (1, 4, 20):
-        ro = Rollout(s, tau, n, ckpt, diss_weight=1e-3)
+    for ckpt, keep in ((1, 1), (4, 1), (20, 1), (2, 2), (2, None), (4, None)):
+        ro = Rollout(s, tau, n, ckpt, diss_weight=1e-3, keep_segments=keep)
         loss = torch.zeros(1, dtype=torch.float64, device="cuda")
         fN = ro.forward(f0, loss)
+        if keep is None:
+            # every state before the last was kept from the forward: the
+            # checkpoints among them as checkpoints, the others in the tail
+            assert sorted(ro.tail) == [m for m in range(1, n) if m % ckpt], (ckpt, sorted(ro.tail))
+            assert sorted(ro.ckpts) == list(range(0, n, ckpt)), (ckpt, sorted(ro.ckpts))
         for rep in range(2 if ckpt == 4 else 1):
             fg = torch.zeros_like(F) if dtype == "f32" else None
             lam0 = ro.backward(fN * 0.5, diss_grad=1.0, force_grad=fg)
-            results.append((f"ckpt {ckpt} backward {rep}", loss.item(), lam0.clone(), fg))
+            assert not ro.tail, "the backward releases the kept states"
+            results.append((f"ckpt {ckpt} keep {keep} backward {rep}", loss.item(), fN.clone(), lam0.clone(), fg))
     ref = results[0]
-    for name, L, lam0, fg in results[1:]:
+    for name, L, fN, lam0, fg in results[1:]:
         _log(f"[rollout schedules] {name}: loss {L:.15e}")
         assert L == ref[1], name
-        assert torch.equal(lam0, ref[2]), name
+        assert torch.equal(fN, ref[2]), name
+        assert torch.equal(lam0, ref[3]), name
         if fg is not None:
-            assert torch.equal(fg, ref[3]), name
+            assert torch.equal(fg, ref[4]), name
 
 
 def test_dot_product_identity(es):
