@@ -271,11 +271,14 @@ def copy_bandwidth(torch, nbytes: int, reps: int = 20):
     return 2 * nbytes / (ms * 1e-3) / 1e9, ms
 
 
-def time_adjoint(es, torch, W, steps: int, ckpt: int):
+def time_adjoint(es, torch, W, steps: int, ckpt: int, reps: int = 3):
     """Forward rollout (with the per-step dissipation loss) and its adjoint
     sweep (recompute + adjoint kernels + loss seeds) on the forced 128^3
     D3Q27 workload, checkpointed every ``ckpt`` steps; then the same with
-    every state kept from the forward (no recompute), where memory allows."""
+    every state kept from the forward (no recompute), where memory allows.
+    Each is run once untimed (first allocations of the caching allocator,
+    the library's loss scratch), then ``reps`` times: the median forward and
+    backward times."""
     from paper_2203_12946_amd.adjoint import Rollout
     wl = W.ADJ3D_128
     rho, u = W.fields_for(wl)
@@ -284,52 +287,50 @@ def time_adjoint(es, torch, W, steps: int, ckpt: int):
     s.set_force(F)
     f0 = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
     nu0 = wl.nu
-    ro = Rollout(s, wl.tau, steps, ckpt, diss_weight=nu0)
     loss = torch.zeros(1, dtype=torch.float64, device="cuda")
-    # one untimed forward and backward each (first allocations of the
-    # caching allocator, the library's loss scratch)
-    ro.forward(f0, loss)
-    ro.backward(None, diss_grad=1.0, force_grad=torch.zeros((3,) + wl.shape, dtype=torch.float32, device="cuda"))
-    torch.cuda.synchronize()
-    loss.zero_()
-    t0 = time.perf_counter()
-    ro.forward(f0, loss)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    fg = torch.zeros((3,) + wl.shape, dtype=torch.float32, device="cuda")
-    t2 = time.perf_counter()
-    ro.backward(None, diss_grad=1.0, force_grad=fg)
-    torch.cuda.synchronize()
-    t3 = time.perf_counter()
-    ok = bool(torch.isfinite(fg).all().item())
-    out = dict(workload=wl.name, steps=steps, ckpt_every=ckpt, forward_s=t1 - t0, backward_s=t3 - t2,
-               ratio=(t3 - t2) / (t1 - t0), loss=float(loss.item()), grad_finite=ok,
-               grad_norm=float(fg.double().norm().item()))
-    del ro
-    # The same gradient with every state of the rollout kept in HBM by the
-    # forward (no recomputation in the backward): the memory for compute
-    # trade a 288 GB device affords at this size.
-    ro = Rollout(s, wl.tau, steps, ckpt, diss_weight=nu0, keep_segments=None)
-    state_gb = steps * s.Q * s.cells * 4 / 1e9
-    if torch.cuda.mem_get_info()[0] > 1.3 * (state_gb + steps * 4 * s.cells * 4 / 1e9):
-        ro.forward(f0, loss)
-        ro.backward(None, diss_grad=1.0, force_grad=torch.zeros_like(fg))
-        torch.cuda.synchronize()
+
+    def run(ro):
         loss.zero_()
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         ro.forward(f0, loss)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        fg2 = torch.zeros_like(fg)
+        fg = torch.zeros((3,) + wl.shape, dtype=torch.float32, device="cuda")
+        torch.cuda.synchronize()
         t2 = time.perf_counter()
-        ro.backward(None, diss_grad=1.0, force_grad=fg2)
+        ro.backward(None, diss_grad=1.0, force_grad=fg)
         torch.cuda.synchronize()
         t3 = time.perf_counter()
-        out["all_states_resident"] = dict(
-            forward_s=t1 - t0, backward_s=t3 - t2, ratio=(t3 - t2) / (t1 - t0), state_gb=round(state_gb, 1),
-            grad_equal_checkpointed=bool(torch.equal(fg2, fg)), loss_equal_checkpointed=bool(loss.item() == out["loss"]))
+        return t1 - t0, t3 - t2, float(loss.item()), fg
+
+    def timed(ro):
+        run(ro)
+        runs = [run(ro) for _ in range(reps)]
+        fwd = sorted(r[0] for r in runs)[reps // 2]
+        bwd = sorted(r[1] for r in runs)[reps // 2]
+        return fwd, bwd, runs[-1][2], runs[-1][3]
+
+    ro = Rollout(s, wl.tau, steps, ckpt, diss_weight=nu0)
+    fwd, bwd, L, fg = timed(ro)
+    out = dict(workload=wl.name, steps=steps, ckpt_every=ckpt, forward_s=fwd, backward_s=bwd, ratio=bwd / fwd,
+               loss=L, grad_finite=bool(torch.isfinite(fg).all().item()),
+               grad_norm=float(fg.double().norm().item()), timing=f"median of {reps}")
     del ro
     torch.cuda.empty_cache()
+    # The same gradient with every state of the rollout kept in HBM by the
+    # forward (no recomputation in the backward): the memory for compute
+    # trade a 288 GB device affords at this size.
+    state_gb = steps * s.Q * s.cells * 4 / 1e9
+    if torch.cuda.mem_get_info()[0] > 1.3 * (state_gb + steps * 4 * s.cells * 4 / 1e9):
+        ro = Rollout(s, wl.tau, steps, ckpt, diss_weight=nu0, keep_segments=None)
+        fwd2, bwd2, L2, fg2 = timed(ro)
+        out["all_states_resident"] = dict(
+            forward_s=fwd2, backward_s=bwd2, ratio=bwd2 / fwd2, state_gb=round(state_gb, 1),
+            timing=f"median of {reps}", grad_equal_checkpointed=bool(torch.equal(fg2, fg)),
+            loss_equal_checkpointed=bool(L2 == L))
+        del ro
+        torch.cuda.empty_cache()
     return out
 
 
