@@ -155,11 +155,18 @@ __device__ inline bool quasi_equilibrium(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>:
     int it = 0;
     for (; it < QECfg<E>::maxit && !conv; ++it) {
         // r_i = feq_i expm1(delta . phi_i): its moments give the residual,
-        // and with those of feq the Jacobian's (f^QE = feq + r)
+        // and with those of feq the Jacobian's (f^QE = feq + r).  The first
+        // step starts from delta = 0, where r = 0: its moments are zero
+        // without evaluating the Q exponentials.
         E mr[Q];
+        if (it == 0) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_(qe_arg<D, E>(i, delta));
-        contract_rows<D, E>(mr);
+            for (int i = 0; i < Q; ++i) mr[i] = E(0);
+        } else {
+#pragma unroll
+            for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_(qe_arg<D, E>(i, delta));
+            contract_rows<D, E>(mr);
+        }
         // Cholesky of J_kl = sum f^QE phi_k phi_l, packed lower triangle
         float L[K * (K + 1) / 2];
 #pragma unroll
