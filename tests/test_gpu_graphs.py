@@ -36,10 +36,14 @@ def _eager(s, f0, tau, n, ckpt, diss, lamN, with_fg):
     return fN.clone(), loss.clone(), lam0.clone(), None if fg is None else fg.clone()
 
 
-@pytest.mark.parametrize("case", ["d3q27_forced_dissipation", "d2q9_final_state"])
+@pytest.mark.parametrize("case", ["d3q27_forced_dissipation", "d3q27_forced_dissipation_all_kept", "d2q9_final_state"])
 def test_graphed_rollout_replays_equal_eager(es, case):
+    """(The all_kept case captures a rollout that keeps every state from its
+    forward sweep, and compares it with the default eager rollout, which
+    recomputes them.)"""
     from paper_2203_12946_amd.adjoint import GraphedRollout
-    if case == "d3q27_forced_dissipation":
+    keep = None if case.endswith("all_kept") else 1
+    if case.startswith("d3q27_forced_dissipation"):
         shape, lat, n, ckpt, diss, tau = (5, 6, 70), "D3Q27", 9, 4, 1e-3, 2e-3
         fields = [W.taylor_green_3d(0, shape=shape, u0=0.08, noise=1e-3, seed=sd) for sd in (51, 52)]
     else:
@@ -53,7 +57,7 @@ def test_graphed_rollout_replays_equal_eager(es, case):
                               torch.from_numpy(np.ascontiguousarray(u)).cuda()) for r, u in fields]
     lamN = torch.from_numpy(np.random.default_rng(56).standard_normal((s.Q,) + shape)).float().cuda() * 1e-3
     refs = [_eager(s, f0, tau, n, ckpt, diss, lamN, with_fg) for f0 in f0s]
-    g = GraphedRollout(s, f0s[0], tau, n, ckpt, diss_weight=diss, with_force_grad=with_fg)
+    g = GraphedRollout(s, f0s[0], tau, n, ckpt, diss_weight=diss, with_force_grad=with_fg, keep_segments=keep)
     g.lam_final.copy_(lamN)
     for rep, k in enumerate((0, 1, 1, 0, 1)):
         g.f0.copy_(f0s[k])
