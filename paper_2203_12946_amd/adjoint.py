@@ -221,7 +221,9 @@ class GraphedRollout:
     capture, and leaves the adjoint of ``f0`` in ``lam0`` and, with
     ``with_force_grad``, the gradient with respect to the solver's
     registered force in ``force_grad``.  A backward replay uses the states of
-    the last forward replay.
+    the last forward replay; ``keep_segments`` chooses, as in ``Rollout``,
+    which of them the forward graph keeps rather than the backward graph
+    recomputing them.
 
     A replay relaunches the captured kernels on the same buffers: its results
     equal an eager rollout's bit for bit.  The solver's settings at capture
