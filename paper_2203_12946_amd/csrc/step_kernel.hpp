@@ -134,7 +134,12 @@ __device__ inline void block_reduce_stats(LaneStats &s, DevStats *slot)
 //    removes, about 1e-8 of w per step, lies far below the unbiased storage
 //    rounding of every stored deviation (about 1e-5 of w per step), which
 //    conserves mass and momentum only on average anyway, and the step is
-//    bound by VALU issue; F64: every part is double already.
+//    bound by VALU issue.  For the same reason it drops two register devices
+//    that cost it moves (pin_dev false, zeros_in_branch true: 55 fewer VALU
+//    instructions per wave); in the other formats those choices leave the
+//    registers as they are (F32-shifted spills on its common path without
+//    them) or make no measurable difference; F64: every part is double
+//    already.
 // The kernel is a stream of Q loads and Q stores per lane and needs several
 // waves per SIMD in flight to cover HBM latency: 4 waves (<= 128 VGPRs) for
 // the 4- and 2-byte formats; the double moments and equilibrium of
@@ -151,6 +156,7 @@ template <typename S>
 struct StepPolicy {
     static constexpr int waves = 4;
     static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false, conserve = true;
+    static constexpr bool pin_dev = true, zeros_in_branch = false;
     static constexpr int stash = 0, stash_waves = 0;
     using Series = SeriesCfg<typename Storage<S>::T>;
     using Exact = double;
@@ -159,6 +165,7 @@ template <>
 struct StepPolicy<f32s> {
     static constexpr int waves = 4;
     static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = true, conserve = true;
+    static constexpr bool pin_dev = true, zeros_in_branch = false;
     static constexpr int stash = 0, stash_waves = 0;
     using Series = SeriesCfg<float>;
     using Exact = double;
@@ -167,6 +174,7 @@ template <>
 struct StepPolicy<_Float16> {
     static constexpr int waves = 4;
     static constexpr bool mom_f64 = false, eq_f64 = false, ab_split = false, conserve = false;
+    static constexpr bool pin_dev = false, zeros_in_branch = true;
     static constexpr int stash = 0, stash_waves = 0;
     using Series = SeriesCfgF16;
     using Exact = float;
@@ -175,6 +183,7 @@ template <>
 struct StepPolicy<double> {
     static constexpr int waves = 2;
     static constexpr bool mom_f64 = true, eq_f64 = true, ab_split = false, conserve = true;
+    static constexpr bool pin_dev = true, zeros_in_branch = false;
     static constexpr int stash = 24, stash_waves = 3;
     using Series = SeriesCfg<double>;
     using Exact = double;
@@ -204,7 +213,7 @@ constexpr int stash_pops()
 // and (CONSERVE) its mass and momentum then made exact to rounding.
 // With POLY the equilibrium is the polynomial one of Eq. histeq (the classic
 // LBGK mode): feq_i - w_i = w_i (drho + rho (3 c.u + 4.5 (c.u)^2 - 1.5 u^2)).
-template <int D, typename T, typename EQ, bool POLY, bool CONSERVE, typename Dev>
+template <int D, typename T, typename EQ, bool POLY, bool CONSERVE, bool PIN, typename Dev>
 __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)[Lat<D>::Q])
 {
     const EQ rho = EQ(1) + drho, ir = rcp_(rho);
@@ -214,10 +223,12 @@ __device__ inline void form_deviation(Dev dev, EQ drho, const EQ (&j)[3], T (&d)
 #pragma unroll
     for (int i = 0; i < Lat<D>::Q; ++i) {
         // the stored deviation is formed again rather than kept live since
-        // the moment sums (the empty asm hides it from common-subexpression
-        // elimination and emits nothing)
+        // the moment sums (PIN: the empty asm hides it from
+        // common-subexpression elimination and emits nothing; shifted storage
+        // holds the deviation itself, which there is nothing to form again,
+        // and the asm would only copy it)
         T v = dev(i);
-        asm volatile("" : "+v"(v));
+        if constexpr (PIN) asm volatile("" : "+v"(v));
         EQ fe;
         if (POLY) {
             EQ cu = EQ(0);
@@ -506,8 +517,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
             // fixed function of the cell's state, so it acts as a bias that
             // accumulates over steps.  The path length stays in T.
             using EQ = typename std::conditional<Pol::eq_f64, double, T>::type;
-            form_deviation<D, T, EQ, MODE == MODE_LBGK, Pol::conserve>(pdev, EQ(drhoE),
-                                                                      {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
+            form_deviation<D, T, EQ, MODE == MODE_LBGK, Pol::conserve, Pol::pin_dev>(pdev, EQ(drhoE),
+                                                                                    {EQ(jE[0]), EQ(jE[1]), EQ(jE[2])}, dd);
             // ES-BGK: the quasi-equilibrium replaces the equilibrium, and the
             // path length is found from x = f^QE / g - 1 as before
             int qe_it = 0;
@@ -539,7 +550,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(step_waves_
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) dd[i] = T(0);
+            for (int i = 0; i < Q; ++i) {
+                dd[i] = T(0);
+                // (zeros_in_branch: the empty asm keeps the zeros in this
+                // branch; hoisted above it, they cost every wave Q moves that
+                // only uncollided lanes need)
+                if constexpr (Pol::zeros_in_branch) asm volatile("" : "+v"(dd[i]));
+            }
         }
         // post-collision value p + alpha beta (feq - g) [+ force term]
 #pragma unroll
