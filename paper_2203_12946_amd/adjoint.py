@@ -14,7 +14,9 @@ schedules them:
   velocity field of every checkpoint: the backward sweep starts from them.
   ``keep_segments=None`` keeps every state, so that the backward recomputes
   nothing (at 128^3 D3Q27 in single precision, 500 states take 113 GB of
-  the 288 GB of HBM).
+  the 288 GB of HBM); ``keep_segments='auto'`` keeps as many trailing
+  segments as fit a memory budget (by default 80% of the free device
+  memory when the forward starts).
 * ``Rollout.backward`` sweeps the checkpoint segments in reverse.  For each
   segment whose states were not kept it recomputes them from its checkpoint
   (with their velocity fields).  It then applies the adjoint step kernel from the
@@ -41,17 +43,22 @@ from .eselbm import Solver
 
 class Rollout:
     def __init__(self, solver: Solver, tau: float, nsteps: int, ckpt_every: int,
-                 diss_weight: float | None = None, keep_segments: int | None = 1):
+                 diss_weight: float | None = None, keep_segments: int | str | None = 1,
+                 memory_budget: float | None = None):
         if nsteps < 1 or ckpt_every < 1:
             raise ValueError("nsteps and ckpt_every must be >= 1")
-        if keep_segments is not None and int(keep_segments) < 1:
-            raise ValueError("keep_segments must be >= 1 or None")
+        if keep_segments == "auto":
+            pass
+        elif keep_segments is not None and (isinstance(keep_segments, str) or int(keep_segments) < 1):
+            raise ValueError("keep_segments must be >= 1, None or 'auto'")
         self.s = solver
         self.tau = float(tau)
         self.nsteps = int(nsteps)
         self.K = int(ckpt_every)
         self.diss_weight = diss_weight
-        self.keep_segments = None if keep_segments is None else int(keep_segments)
+        self.keep_segments = keep_segments if keep_segments in (None, "auto") else int(keep_segments)
+        self.memory_budget = memory_budget
+        self.kept = self.keep_segments if self.keep_segments != "auto" else 1
         self.ckpts: dict[int, torch.Tensor] = {}
         # velocity fields of the checkpoints (with the loss), and the states
         # of the last segment after its checkpoint with their velocity fields
@@ -72,18 +79,39 @@ class Rollout:
         """First state of the last checkpoint segment."""
         return ((self.nsteps - 1) // self.K) * self.K
 
+    def _resolve_kept(self) -> int | None:
+        """The trailing segments the forward keeps: keep_segments, or with
+        'auto' as many as fit the memory budget (bytes; by default 80% of the
+        device memory free now, the caching allocator's unused reserve
+        included), at least one; None when that is all of them."""
+        if self.keep_segments != "auto":
+            return self.keep_segments
+        s = self.s
+        per_state = s.Q * s.cells * torch.empty((), dtype=s.storage_dtype).element_size()
+        if self.diss_weight is not None:
+            per_state += (s.D + 1) * s.cells * 4
+        budget = self.memory_budget
+        if budget is None:
+            free, _ = torch.cuda.mem_get_info(s.device)
+            free += torch.cuda.memory_reserved(s.device) - torch.cuda.memory_allocated(s.device)
+            budget = 0.8 * free
+        nseg = (self.nsteps + self.K - 1) // self.K
+        k = max(1, int(budget // (self.K * per_state)))
+        return None if k >= nseg else k
+
     def _kept_start(self) -> int:
         """First state (a checkpoint) of the first segment whose states the
         forward keeps."""
-        if self.keep_segments is None:
+        if self.kept is None:
             return 0
-        return max(0, self._last_start() - (self.keep_segments - 1) * self.K)
+        return max(0, self._last_start() - (self.kept - 1) * self.K)
 
     def forward(self, f0: torch.Tensor, loss_acc: torch.Tensor | None = None) -> torch.Tensor:
         """State after nsteps; with a dissipation weight, adds the loss of
         every state f^1..f^n to ``loss_acc`` (a device float64 scalar)."""
         s = self.s
         self.ckpts, self.ckpt_uv, self.tail, self.uv_end = {}, {}, {}, None
+        self.kept = self._resolve_kept()
         cur = f0.clone()
         nxt = s.empty_state()
         self.ckpts[0] = cur.clone()
@@ -236,7 +264,7 @@ class GraphedRollout:
 
     def __init__(self, solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
                  diss_weight: float | None = None, diss_grad: float = 1.0, with_force_grad: bool = False,
-                 keep_segments: int | None = 1):
+                 keep_segments: int | str | None = 1):
         s = solver
         self.ro = Rollout(s, tau, nsteps, ckpt_every, diss_weight, keep_segments)
         self.f0 = f0.detach().clone()
@@ -350,11 +378,12 @@ def equilibrium(solver: Solver, rho: torch.Tensor, u: torch.Tensor) -> torch.Ten
 
 def rollout(solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
             force: torch.Tensor | None = None, diss_weight: float | None = None,
-            keep_segments: int | None = 1):
+            keep_segments: int | str | None = 1):
     """(state after nsteps, accumulated dissipation loss).  ``force`` becomes
     the solver's registered body force for the rollout; None clears it.
     ``keep_segments``: the trailing checkpoint segments whose states the
-    forward keeps for the backward (None: all of them, no recomputation)."""
+    forward keeps for the backward (None: all of them, no recomputation;
+    'auto': as many as fit 80% of the free device memory)."""
     return _Rollout.apply(f0, force, solver, tau, nsteps, ckpt_every, diss_weight, keep_segments)
 
 

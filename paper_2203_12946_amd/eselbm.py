@@ -369,7 +369,7 @@ def beta_of_tau(tau: float) -> float:
 
 def rollout(solver: Solver, f0: torch.Tensor, tau: float, nsteps: int, ckpt_every: int,
             force: torch.Tensor | None = None, diss_weight: float | None = None,
-            keep_segments: int | None = 1):
+            keep_segments: int | str | None = 1):
     """Differentiable checkpointed rollout: (state after nsteps, accumulated
     dissipation loss); see paper_2203_12946_amd.adjoint.rollout."""
     from .adjoint import rollout as _rollout

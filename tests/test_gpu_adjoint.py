@@ -442,8 +442,9 @@ def test_rollout_schedules_agree(es, dtype):
     rollout with the dissipation loss over 7 steps, checkpointed every 1, 4
     and 20 steps (every state a checkpoint; a last segment of three states,
     two of them kept by the forward; one segment that the forward keeps
-    whole), and every 2 steps with the last two segments kept or every state
-    kept (no recomputation), gives the same bits, and so does a second
+    whole), and every 2 steps with the last two segments kept, every state
+    kept (no recomputation) or as many as the free memory holds, gives the
+    same bits, and so does a second
     backward of one forward (it recomputes the states the first one used and
     released).  In single precision, with a body force, the adjoint steps form
     the loss seeds themselves; in double precision, unforced, seed passes
@@ -459,7 +460,7 @@ def test_rollout_schedules_agree(es, dtype):
         s.set_force(F)
     f0 = s.init_equilibrium(torch.from_numpy(rho).cuda(), torch.from_numpy(u).cuda())
     results = []
-    for ckpt, keep in ((1, 1), (4, 1), (20, 1), (2, 2), (2, None), (4, None)):
+    for ckpt, keep in ((1, 1), (4, 1), (20, 1), (2, 2), (2, None), (4, None), (2, "auto")):
         ro = Rollout(s, tau, n, ckpt, diss_weight=1e-3, keep_segments=keep)
         loss = torch.zeros(1, dtype=torch.float64, device="cuda")
         fN = ro.forward(f0, loss)

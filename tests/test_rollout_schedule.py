@@ -15,6 +15,8 @@ from paper_2203_12946_amd.adjoint import Rollout
 
 class StandInSolver:
     compute_dtype = torch.float32
+    storage_dtype = torch.float32
+    D, Q, cells = 3, 1, 4  # a state of 16 bytes, a velocity field of 64
 
     def __init__(self):
         self.steps = 0
@@ -76,9 +78,25 @@ def test_full_length_rollout_recompute_counts():
         assert s.steps - 500 == recomputed, keep
 
 
+@pytest.mark.parametrize("budget,recomputed", [(0, 441), (80 * 50 * 3, 343), (80 * 50 * 3 + 79, 343),
+                                               (80 * 50 * 9, 49), (80 * 50 * 10, 0), (1e12, 0)])
+def test_auto_keeps_what_the_budget_holds(budget, recomputed):
+    """keep_segments='auto': as many trailing segments of 50 states (80
+    bytes each with the velocity field) as the budget holds, at least one;
+    with all ten the backward recomputes nothing."""
+    s = StandInSolver()
+    ro = Rollout(s, 0.1, 500, 50, diss_weight=1e-3, keep_segments="auto", memory_budget=budget)
+    ro.forward(torch.zeros(4), torch.zeros(1, dtype=torch.float64))
+    ro.backward(None, diss_grad=1.0)
+    assert s.steps - 500 == recomputed
+    assert s.adjoint_calls == [(m, m + 1) for m in range(499, -1, -1)]
+
+
 def test_rollout_arguments():
     with pytest.raises(ValueError):
         Rollout(StandInSolver(), 0.1, 10, 5, keep_segments=0)
+    with pytest.raises(ValueError):
+        Rollout(StandInSolver(), 0.1, 10, 5, keep_segments="all")
     with pytest.raises(ValueError):
         Rollout(StandInSolver(), 0.1, 0, 5)
     with pytest.raises(ValueError):
