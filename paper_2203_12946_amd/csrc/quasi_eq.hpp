@@ -33,6 +33,37 @@ namespace eselbm {
 __device__ inline float expm1_(float v) { return expm1f(v); }
 __device__ inline double expm1_(double v) { return expm1(v); }
 
+// expm1 for |v| <= 1/32 by its Taylor polynomial: truncated after v^N its
+// relative error is below |v|^N / (N+1)! <= 4e-11 (float, N = 5) and 8e-21
+// (double, N = 9), under the rounding of the type.  Near equilibrium every
+// exponent delta . phi_i of a cell lies in that range (|delta . phi_i| <=
+// sum_k |delta_k|, since phi_ik is 0 or +-1).
+template <typename E>
+struct SmallExpm1;
+template <>
+struct SmallExpm1<float> {
+    static constexpr int N = 5;
+};
+template <>
+struct SmallExpm1<double> {
+    static constexpr int N = 9;
+};
+template <typename E>
+__device__ inline E expm1_small(E v)
+{
+    constexpr int N = SmallExpm1<E>::N;
+    // 1/k! for k = 1..N
+    double inv_fact[N + 1];
+    inv_fact[0] = 1.0;
+#pragma unroll
+    for (int k = 1; k <= N; ++k) inv_fact[k] = inv_fact[k - 1] / k;
+    E p = E(inv_fact[N]);
+#pragma unroll
+    for (int k = N - 1; k >= 1; --k) p = fma_(p, v, E(inv_fact[k]));
+    return p * v;
+}
+constexpr double kSmallExpArg = 1.0 / 32.0;
+
 template <int D>
 struct QEBasis {
     static constexpr int K = D == 2 ? 6 : 10;
@@ -151,6 +182,15 @@ __device__ inline bool quasi_equilibrium(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>:
     E delta[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) delta[k] = E(0);
+    // true in every lane when every lane's exponents delta . phi_i are within
+    // the range of expm1_small (a wave-uniform choice, so that the wave takes
+    // one of the two forms)
+    auto small_exponents = [](const E (&dl)[K]) {
+        E bound = E(0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) bound += abs_(dl[k]);
+        return __ballot(!(bound <= E(kSmallExpArg))) == 0ull;
+    };
     bool conv = false;
     int it = 0;
     for (; it < QECfg<E>::maxit && !conv; ++it) {
@@ -163,8 +203,13 @@ __device__ inline bool quasi_equilibrium(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>:
 #pragma unroll
             for (int i = 0; i < Q; ++i) mr[i] = E(0);
         } else {
+            if (small_exponents(delta)) {
 #pragma unroll
-            for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_(qe_arg<D, E>(i, delta));
+                for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_small(qe_arg<D, E>(i, delta));
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_(qe_arg<D, E>(i, delta));
+            }
             contract_rows<D, E>(mr);
         }
         // Cholesky of J_kl = sum f^QE phi_k phi_l, packed lower triangle
@@ -215,8 +260,13 @@ __device__ inline bool quasi_equilibrium(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>:
     }
     iters = it;
     if (!conv) return false;
+    if (small_exponents(delta)) {
 #pragma unroll
-    for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_(qe_arg<D, E>(i, delta)));
+        for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_small(qe_arg<D, E>(i, delta)));
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_(qe_arg<D, E>(i, delta)));
+    }
     conserve_moments<D, T>(d);
     return true;
 }
