@@ -120,19 +120,60 @@ __device__ inline void contract_rows(V (&m)[Lat<D>::Q])
     }
 }
 
-// delta . phi_i, with phi_i's entries compile-time after unrolling
+// The exponents delta . phi_i of a cell, grouped by axis.  With the basis
+// ordered (1, c_x, c_y[, c_z], c_x^2, c_x c_y[, c_x c_z], c_y^2[, c_y c_z,
+// c_z^2]) (QEBasis),
+//   delta . phi_i = X(c_x) + R(c_y, c_z) + c_x G(c_y, c_z),
+// X holding the terms in c_x alone (and the constant), R those in c_y and
+// c_z alone, G the coefficients of the mixed products with c_x: 3 + 2 x 3^(D-1)
+// values formed once, then one or two additions per population instead of a
+// sum over the K basis functions.
 template <int D, typename E>
-__device__ inline E qe_arg(int i, const E (&delta)[QEBasis<D>::K])
-{
-    E s = E(0);
+struct QEArgs {
+    E X[3], R[D == 3 ? 9 : 3], G[D == 3 ? 9 : 3];
+    __device__ explicit QEArgs(const E (&dl)[QEBasis<D>::K])
+    {
+        // basis indices: D = 3: 0 1, 1 x, 2 y, 3 z, 4 xx, 5 xy, 6 xz, 7 yy,
+        // 8 yz, 9 zz; D = 2: 0 1, 1 x, 2 y, 3 xx, 4 xy, 5 yy
+        constexpr int XX = D == 3 ? 4 : 3, XY = D == 3 ? 5 : 4, YY = D == 3 ? 7 : 5;
+        X[0] = (dl[0] - dl[1]) + dl[XX];
+        X[1] = dl[0];
+        X[2] = (dl[0] + dl[1]) + dl[XX];
+        const E Y[3] = {dl[YY] - dl[2], E(0), dl[YY] + dl[2]};
+        if constexpr (D == 3) {
+            const E Z[3] = {dl[9] - dl[3], E(0), dl[9] + dl[3]};
 #pragma unroll
-    for (int k = 0; k < QEBasis<D>::K; ++k) {
-        const int ph = QEBasis<D>::phi(k, i);
-        if (ph == 1) s += delta[k];
-        else if (ph == -1) s -= delta[k];
+            for (int cz = -1; cz <= 1; ++cz)
+#pragma unroll
+                for (int cy = -1; cy <= 1; ++cy) {
+                    const int r = (cy + 1) + 3 * (cz + 1);
+                    E rv = Y[cy + 1] + Z[cz + 1];
+                    if (cy * cz > 0) rv += dl[8];
+                    if (cy * cz < 0) rv -= dl[8];
+                    R[r] = rv;
+                    E g = E(0);
+                    if (cy > 0) g += dl[XY];
+                    if (cy < 0) g -= dl[XY];
+                    if (cz > 0) g += dl[6];
+                    if (cz < 0) g -= dl[6];
+                    G[r] = g;
+                }
+        } else {
+#pragma unroll
+            for (int cy = -1; cy <= 1; ++cy) {
+                R[cy + 1] = Y[cy + 1];
+                G[cy + 1] = cy > 0 ? dl[XY] : (cy < 0 ? -dl[XY] : E(0));
+            }
+        }
     }
-    return s;
-}
+    // delta . phi_i (i compile-time after unrolling)
+    __device__ E operator()(int i) const
+    {
+        const int cx = Lat<D>::c(i, 0), r = (Lat<D>::c(i, 1) + 1) + 3 * (D == 3 ? Lat<D>::c(i, 2) + 1 : 0);
+        if (cx == 0) return X[1] + R[r];
+        return cx > 0 ? (X[2] + R[r]) + G[r] : (X[0] + R[r]) - G[r];
+    }
+};
 
 template <typename E>
 struct QECfg;
@@ -203,12 +244,13 @@ __device__ inline bool quasi_equilibrium(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>:
 #pragma unroll
             for (int i = 0; i < Q; ++i) mr[i] = E(0);
         } else {
+            const QEArgs<D, E> qa(delta);
             if (small_exponents(delta)) {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_small(qe_arg<D, E>(i, delta));
+                for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_small(qa(i));
             } else {
 #pragma unroll
-                for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_(qe_arg<D, E>(i, delta));
+                for (int i = 0; i < Q; ++i) mr[i] = fe(i) * expm1_(qa(i));
             }
             contract_rows<D, E>(mr);
         }
@@ -260,12 +302,13 @@ __device__ inline bool quasi_equilibrium(const T (&p)[Lat<D>::Q], T (&d)[Lat<D>:
     }
     iters = it;
     if (!conv) return false;
+    const QEArgs<D, E> qa(delta);
     if (small_exponents(delta)) {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_small(qe_arg<D, E>(i, delta)));
+        for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_small(qa(i)));
     } else {
 #pragma unroll
-        for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_(qe_arg<D, E>(i, delta)));
+        for (int i = 0; i < Q; ++i) d[i] = T(E(d[i]) + fe(i) * expm1_(qa(i)));
     }
     conserve_moments<D, T>(d);
     return true;
