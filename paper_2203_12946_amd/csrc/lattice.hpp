@@ -631,10 +631,14 @@ __device__ __attribute__((always_inline)) inline A mirror_alpha(const P &p, cons
     auto xof = [&](int i) { return A(d[i]) * rcp_(A(gval<D, T, SH>(i, p))); };
     A S = A(0), xa = A(0);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const A x = xof(i);
-        S = fma_(A(d[i]), log1p_(x), S);
-        xa = fmax_(xa, abs_(x));
+    for (int i = 0; i < Q; ++i) xa = fmax_(xa, abs_(xof(i)));
+    // S by the series of log(1 + x) where every x of the wave is in its range
+    if (__ballot(!(xa < A(MirrorCfg<A>::Y))) == 0ull) {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) S = fma_(A(d[i]), log1p_series(xof(i)), S);
+    } else {
+#pragma unroll
+        for (int i = 0; i < Q; ++i) S = fma_(A(d[i]), log1p_(xof(i)), S);
     }
     const A astar = A(-1) * rcp_(xmin);
     A lo = A(1), hi = astar;
