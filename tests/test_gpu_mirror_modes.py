@@ -148,6 +148,45 @@ def test_elbm_smooth_flow_no_fallback(es, dtype):
     assert da <= (1e-9 if dtype == "f64" else 1e-5)
 
 
+@pytest.mark.parametrize("mode", ["elbm", "iterate1"])
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_mirror_modes_rollout_3d(es, mode, dtype):
+    """40 steps of a 3-D Taylor-Green vortex (12 x 14 x 16, u0 = 0.05) in the
+    mirror-condition modes: near equilibrium every wave's arguments of the
+    logarithms lie in the series range, so the iteration and the sum S take
+    their series forms throughout; against the oracle's rollout (FP64 to
+    1e-11; F32 within 4x the oracle's own error when its storage is rounded
+    after every step)."""
+    shape, steps, tau = (12, 14, 16), 40, 0.01
+    rho, u = W.taylor_green_3d(0, shape=shape, u0=0.05, noise=1e-3, seed=22)
+    f0 = oracle.init_equilibrium(rho, u)
+    ref = oracle.step(f0, steps, tau, mode=mode)
+    rr, ru = oracle.moments(ref)
+    s = es.Solver("D3Q27", shape, dtype=dtype, mode=mode)
+    a = s.init_equilibrium(torch.from_numpy(np.ascontiguousarray(rho)).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(u)).cuda())
+    b = s.empty_state()
+    s.set_stats(True)
+    s.step(a, b, steps, tau)
+    st = s.stats()
+    gr, gu = s.moments(b)
+    torch.cuda.synchronize()
+    drho = float(np.max(np.abs(gr.cpu().numpy() - rr)))
+    du = float(np.linalg.norm(gu.cpu().numpy() - ru) / np.linalg.norm(ru))
+    _log(f"[{mode} rollout 3d {dtype}] drho={drho:.2e} du={du:.2e} fallback {st['n_mirror_fallback']}")
+    if dtype == "f64":
+        assert drho <= 1e-11 and du <= 1e-11
+    else:
+        f = _rounded(f0, dtype)
+        for _ in range(steps):
+            f = _rounded(oracle.step(f, 1, tau, mode=mode), dtype)
+        er, eu = oracle.moments(f)
+        fr = float(np.max(np.abs(er - rr)))
+        fu = float(np.linalg.norm(eu - ru) / np.linalg.norm(ru))
+        _log(f"    storage-rounding-only {fr:.2e} {fu:.2e}")
+        assert drho <= 4 * fr and du <= 4 * fu
+
+
 def test_elbm_shear_layer_rollout_f64(es):
     """A 2-D doubly periodic shear layer (Sec. V B) on a 128 x 96 grid at
     nu = 1e-4, 200 ELBM steps in double precision: rho, u within 1e-11 and
